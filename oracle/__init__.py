@@ -1,0 +1,9 @@
+"""CPU oracle of the lane-detection hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  The GPU library never imports, links or calls it.
+"""
+from .ldref import (  # noqa: F401
+    Params, band, build, default_params, detect, energy, fit, lib, m0m1, peaks, philox, ransac,
+    road_edges, road_tables, row_dp, sample, sobel, vdisp_dp, vdisp_hist, votes, weights,
+)

@@ -1,0 +1,345 @@
+"""ctypes binding of the C++ oracle (oracle/ldref.cpp) -- TEST INFRASTRUCTURE ONLY.
+
+Every function here runs the plain FP64 CPU reference of one step of the method, on host
+numpy arrays.  See ldref.cpp for the passage of the paper each step follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ldref.cpp")
+_SO = os.path.join(_HERE, "libldref.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no contraction, no fast-math)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("chi", C.c_int32), ("tau_y_max", C.c_int32), ("tau_x_max", C.c_int32),
+        ("lambda_y", C.c_int32), ("lambda_x", C.c_int32),
+        ("tr_y", C.c_double), ("tr_x", C.c_double),
+        ("eps_num", C.c_int32), ("eps_den", C.c_int32),
+        ("varpi", C.c_double), ("edge_t", C.c_int32), ("sigma_g", C.c_double),
+        ("nu", C.c_int32), ("varsigma", C.c_int32),
+        ("n_hyp", C.c_int32), ("max_rounds", C.c_int32),
+        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+class FitOut(C.Structure):
+    _fields_ = [("ok", C.c_int32), ("flags", C.c_int32), ("center", C.c_int32), ("kshift", C.c_int32),
+                ("rounds", C.c_int32), ("n_survivors", C.c_int32),
+                ("coef", C.c_double * 5), ("raw", C.c_double * 5)]
+
+
+_P32 = C.POINTER(C.c_int32)
+_PD = C.POINTER(C.c_double)
+
+
+class Out(C.Structure):
+    _fields_ = [
+        ("flags", C.c_int32), ("v_h", C.c_int32), ("v_end", C.c_int32), ("n_lanes", C.c_int32),
+        ("n_my", C.c_int32), ("n_edges", C.c_int32), ("n_votes", C.c_int32), ("pad0", C.c_int32),
+        ("u_start", C.c_int32 * 16), ("energy_lane", C.c_double * 16),
+        ("beta", FitOut), ("gamma", FitOut),
+        ("m_y", _P32), ("my_path_v", _P32), ("my_x", _P32), ("my_y", _P32),
+        ("f", _PD), ("fp", _PD), ("vpy", _PD), ("vpx", _PD),
+        ("edge_u", _P32), ("edge_v", _P32), ("edge_gx", _P32), ("edge_gy", _P32), ("edge_bin", _P32),
+        ("edge_q", _PD), ("edge_cap", C.c_int32), ("pad1", C.c_int32),
+        ("mx_path", _P32), ("energy", _PD), ("m1", _PD), ("curves", _PD),
+        ("trace_beta", _P32), ("trace_gamma", _P32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = C.CDLL(_SO)
+        L.ldref_params_default.argtypes = [C.POINTER(Params)]
+        L.ldref_philox.argtypes = [C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+        L.ldref_vdisp_hist.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, _P32]
+        L.ldref_vdisp_dp.argtypes = [_P32, C.c_int, C.c_int, C.c_int, C.c_int, _P32, _P32, _P32, _P32]
+        L.ldref_fit.argtypes = [_P32, _P32, _P32, C.c_int, C.c_int, C.c_int32, C.c_int32, _PD]
+        L.ldref_ransac.argtypes = [_P32, _P32, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_uint64, C.c_uint64, C.c_int64, C.c_int, _PD, C.POINTER(FitOut), _P32]
+        L.ldref_road_tables.argtypes = [C.POINTER(FitOut), C.c_int, _PD, _PD, _PD, _P32]
+        L.ldref_sobel.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P32, _P32]
+        _P64 = C.POINTER(C.c_int64)
+        L.ldref_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, _P32]
+        L.ldref_road_edges.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, _PD,
+                                       C.c_int, C.c_double, C.c_int, _P32, _P32, _P32, _P32, C.c_int]
+        L.ldref_votes.argtypes = [_P32, _P32, _P32, _P32, C.c_int, _PD, C.c_int, _P32]
+        L.ldref_band.argtypes = [_P32, C.c_int, C.c_int, C.c_int, C.c_int, _P64]
+        L.ldref_row_dp.argtypes = [_P64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _P32]
+        L.ldref_weights.argtypes = [_P32, _P32, _P32, _P32, C.c_int, _PD, _PD, C.c_double, C.c_int, _PD]
+        L.ldref_m0m1.argtypes = [_PD, C.c_int, C.c_int, C.c_int, C.c_int, _PD, _PD]
+        L.ldref_energy.argtypes = [_PD, _PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD, _P32, C.c_int]
+        L.ldref_peaks.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_int, _P32, _PD]
+        L.ldref_detect.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.POINTER(Params), C.c_uint64, C.c_int64, _PD, C.POINTER(Out)]
+        _lib = L
+    return _lib
+
+
+def _p32(a):
+    return a.ctypes.data_as(_P32)
+
+
+def _pd(a):
+    return a.ctypes.data_as(_PD)
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().ldref_params_default(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def philox(counter, key):
+    ctr = (C.c_uint64 * 4)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in counter])
+    k = (C.c_uint64 * 2)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in key])
+    out = (C.c_uint64 * 4)()
+    lib().ldref_philox(ctr, k, out)
+    return [int(x) for x in out]
+
+
+def _fmt_of(disp: np.ndarray) -> int:
+    return {np.dtype(np.uint8): 0, np.dtype(np.float32): 1, np.dtype(np.uint16): 2}[disp.dtype]
+
+
+def vdisp_hist(disp: np.ndarray, d_max: int) -> np.ndarray:
+    disp = np.ascontiguousarray(disp)
+    H, W = disp.shape
+    out = np.zeros((H, d_max + 1), np.int32)
+    lib().ldref_vdisp_hist(disp.ctypes.data, disp.strides[0], W, H, _fmt_of(disp), d_max, _p32(out))
+    return out
+
+
+def vdisp_dp(m_y: np.ndarray, tau_max: int = 6, lam: int = 1):
+    m_y = np.ascontiguousarray(m_y, dtype=np.int32)
+    H, D1 = m_y.shape
+    path_v = np.zeros(D1, np.int32)
+    px = np.zeros(D1, np.int32)
+    py = np.zeros(D1, np.int32)
+    n = np.zeros(1, np.int32)
+    lib().ldref_vdisp_dp(_p32(m_y), H, D1 - 1, tau_max, lam, _p32(path_v), _p32(px), _p32(py), _p32(n))
+    k = int(n[0])
+    return path_v, px[:k].copy(), py[:k].copy()
+
+
+def fit(x, y, degree: int, center: int, kshift: int, idx=None):
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    coef = np.zeros(degree + 1, np.float64)
+    if idx is None:
+        rc = lib().ldref_fit(_p32(x), _p32(y), None, len(x), degree, center, kshift, _pd(coef))
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        rc = lib().ldref_fit(_p32(x), _p32(y), _p32(idx), len(idx), degree, center, kshift, _pd(coef))
+    return rc, coef
+
+
+def ransac(x, y, degree: int, tr: float, *, n_hyp=64, max_rounds=16, eps=(99, 100), seed=0, stream_id=0,
+           frame_idx=0, stage=0, seed_raw=None):
+    x = np.ascontiguousarray(x, dtype=np.int32)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    out = FitOut()
+    trace = np.full(3 * max_rounds, -9, np.int32)
+    sr = None
+    if seed_raw is not None:
+        sr = np.ascontiguousarray(seed_raw, dtype=np.float64)
+    lib().ldref_ransac(_p32(x), _p32(y), len(x), degree, tr, n_hyp, max_rounds, eps[0], eps[1], seed, stream_id,
+                       frame_idx, stage, _pd(sr) if sr is not None else None, C.byref(out), _p32(trace))
+    return out, trace.reshape(max_rounds, 3)[: out.rounds]
+
+
+def sample(n_cur: int, s: int, *, seed=0, stream_id=0, frame_idx=0, stage=0, rnd=0, hyp=0):
+    pick = np.zeros(5, np.int32)
+    got = lib().ldref_sample(n_cur, s, seed, stream_id, frame_idx, stage, rnd, hyp, _p32(pick))
+    return pick[:got].copy()
+
+
+def road_edges(grey, disp, f, v_h: int, varpi=3.0, edge_t=100):
+    grey = np.ascontiguousarray(grey, dtype=np.uint8)
+    disp = np.ascontiguousarray(disp)
+    H, W = grey.shape
+    cap = H * W
+    arrs = [np.zeros(cap, np.int32) for _ in range(4)]
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    n = lib().ldref_road_edges(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H,
+                               _fmt_of(disp), _pd(f), v_h, varpi, edge_t, *[_p32(a) for a in arrs], cap)
+    return [a[:n].copy() for a in arrs]
+
+
+def votes(eu, ev, egx, egy, vpy, W: int):
+    eu, ev, egx, egy = [np.ascontiguousarray(a, dtype=np.int32) for a in (eu, ev, egx, egy)]
+    vpy = np.ascontiguousarray(vpy, dtype=np.float64)
+    b = np.zeros(len(eu), np.int32)
+    lib().ldref_votes(_p32(eu), _p32(ev), _p32(egx), _p32(egy), len(eu), _pd(vpy), W, _p32(b))
+    return b
+
+
+def band(h, v_h: int, chi: int = 25):
+    h = np.ascontiguousarray(h, dtype=np.int32)
+    H, W2 = h.shape
+    mx = np.zeros((H, W2), np.int64)
+    lib().ldref_band(_p32(h), H, W2, v_h, chi, mx.ctypes.data_as(C.POINTER(C.c_int64)))
+    return mx
+
+
+def row_dp(mx, v_h: int, tau_max: int = 5, lam: int = 1):
+    mx = np.ascontiguousarray(mx, dtype=np.int64)
+    H, W2 = mx.shape
+    cpath = np.full(H, -1, np.int32)
+    lib().ldref_row_dp(mx.ctypes.data_as(C.POINTER(C.c_int64)), H, W2, v_h, tau_max, lam, _p32(cpath))
+    return cpath
+
+
+def weights(eu, ev, egx, egy, vpx, vpy, sigma_g=3.5, squared=0):
+    eu, ev, egx, egy = [np.ascontiguousarray(a, dtype=np.int32) for a in (eu, ev, egx, egy)]
+    vpx = np.ascontiguousarray(vpx, dtype=np.float64)
+    vpy = np.ascontiguousarray(vpy, dtype=np.float64)
+    q = np.zeros(len(eu))
+    lib().ldref_weights(_p32(eu), _p32(ev), _p32(egx), _p32(egy), len(eu), _pd(vpx), _pd(vpy), sigma_g, squared,
+                        _pd(q))
+    return q
+
+
+def m0m1(q, nu=1, varsigma=3):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    H, W = q.shape
+    m0 = np.zeros((H, W))
+    m1 = np.zeros((H, W))
+    lib().ldref_m0m1(_pd(q), W, H, nu, varsigma, _pd(m0), _pd(m1))
+    return m0, m1
+
+
+def energy(m1, vpx, vpy, v_h: int, tracks=None):
+    m1 = np.ascontiguousarray(m1, dtype=np.float64)
+    H, W = m1.shape
+    vpx = np.ascontiguousarray(vpx, dtype=np.float64)
+    vpy = np.ascontiguousarray(vpy, dtype=np.float64)
+    E = np.zeros(2 * W)
+    curves = None
+    if tracks is not None:
+        tracks = np.ascontiguousarray(tracks, dtype=np.int32)
+        curves = np.zeros((len(tracks), H))
+    v_end = lib().ldref_energy(_pd(m1), _pd(vpx), _pd(vpy), W, H, v_h, _pd(E),
+                               _pd(curves) if curves is not None else None,
+                               _p32(tracks) if tracks is not None else None, 0 if tracks is None else len(tracks))
+    return E, v_end, curves
+
+
+def peaks(E, W: int, rho=0.25, d_nms=None):
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    if d_nms is None:
+        d_nms = max(8, W // 64)
+    us = np.zeros(16, np.int32)
+    el = np.zeros(16)
+    n = lib().ldref_peaks(_pd(E), len(E), W // 2, rho, d_nms, _p32(us), _pd(el))
+    return us[:n].copy(), el[:n].copy()
+
+
+def road_tables(beta: FitOut, H: int):
+    f = np.zeros(H)
+    fp = np.zeros(H)
+    vpy = np.zeros(H)
+    vh = np.zeros(1, np.int32)
+    lib().ldref_road_tables(C.byref(beta), H, _pd(f), _pd(fp), _pd(vpy), _p32(vh))
+    return f, fp, vpy, int(vh[0])
+
+
+def sobel(grey: np.ndarray):
+    grey = np.ascontiguousarray(grey, dtype=np.uint8)
+    H, W = grey.shape
+    gx = np.zeros((H, W), np.int32)
+    gy = np.zeros((H, W), np.int32)
+    lib().ldref_sobel(grey.ctypes.data, grey.strides[0], W, H, _p32(gx), _p32(gy))
+    return gx, gy
+
+
+class Result:
+    """Plain container for everything ldref_detect reports about one frame."""
+
+
+def detect(grey: np.ndarray, disp: np.ndarray, d_max: int, params: Params | None = None, *, stream_id=0,
+           frame_idx=0, seed_gamma=None, want_m1=False, edge_cap=None):
+    grey = np.ascontiguousarray(grey, dtype=np.uint8)
+    disp = np.ascontiguousarray(disp)
+    H, W = grey.shape
+    if params is None:
+        params = default_params()
+    D1 = d_max + 1
+    cap = edge_cap if edge_cap is not None else H * W
+    r = Result()
+    r.m_y = np.zeros((H, D1), np.int32)
+    r.my_path_v = np.zeros(D1, np.int32)
+    r.my_x = np.zeros(D1, np.int32)
+    r.my_y = np.zeros(D1, np.int32)
+    r.f = np.zeros(H)
+    r.fp = np.zeros(H)
+    r.vpy = np.zeros(H)
+    r.vpx = np.zeros(H)
+    r.edge_u = np.zeros(cap, np.int32)
+    r.edge_v = np.zeros(cap, np.int32)
+    r.edge_gx = np.zeros(cap, np.int32)
+    r.edge_gy = np.zeros(cap, np.int32)
+    r.edge_bin = np.zeros(cap, np.int32)
+    r.edge_q = np.zeros(cap)
+    r.mx_path = np.zeros(H, np.int32)
+    r.energy = np.zeros(2 * W)
+    r.m1 = np.zeros((H, W)) if want_m1 else None
+    r.curves = np.zeros((16, H))
+    r.trace_beta = np.full((params.max_rounds, 3), -9, np.int32)
+    r.trace_gamma = np.full((params.max_rounds, 3), -9, np.int32)
+    o = Out()
+    o.m_y = _p32(r.m_y); o.my_path_v = _p32(r.my_path_v); o.my_x = _p32(r.my_x); o.my_y = _p32(r.my_y)
+    o.f = _pd(r.f); o.fp = _pd(r.fp); o.vpy = _pd(r.vpy); o.vpx = _pd(r.vpx)
+    o.edge_u = _p32(r.edge_u); o.edge_v = _p32(r.edge_v); o.edge_gx = _p32(r.edge_gx); o.edge_gy = _p32(r.edge_gy)
+    o.edge_bin = _p32(r.edge_bin); o.edge_q = _pd(r.edge_q); o.edge_cap = cap
+    o.mx_path = _p32(r.mx_path); o.energy = _pd(r.energy)
+    o.m1 = _pd(r.m1) if want_m1 else None
+    o.curves = _pd(r.curves)
+    o.trace_beta = _p32(r.trace_beta); o.trace_gamma = _p32(r.trace_gamma)
+    sg = None
+    if seed_gamma is not None:
+        sg = np.ascontiguousarray(seed_gamma, dtype=np.float64)
+    fmt = _fmt_of(disp)
+    lib().ldref_detect(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H, fmt, d_max,
+                       C.byref(params), stream_id, frame_idx, _pd(sg) if sg is not None else None, C.byref(o))
+    r.flags, r.v_h, r.v_end, r.n_lanes = o.flags, o.v_h, o.v_end, o.n_lanes
+    r.n_my, r.n_edges, r.n_votes = o.n_my, o.n_edges, o.n_votes
+    r.my_x = r.my_x[: o.n_my]
+    r.my_y = r.my_y[: o.n_my]
+    n = min(o.n_edges, cap)
+    for nm in ("edge_u", "edge_v", "edge_gx", "edge_gy", "edge_bin", "edge_q"):
+        setattr(r, nm, getattr(r, nm)[:n].copy())
+    r.u_start = np.array(o.u_start[: o.n_lanes], np.int32)
+    r.energy_lane = np.array(o.energy_lane[: o.n_lanes])
+    r.curves = r.curves[: o.n_lanes]
+    r.beta = o.beta
+    r.gamma = o.gamma
+    r.trace_beta = r.trace_beta[: o.beta.rounds]
+    r.trace_gamma = r.trace_gamma[: o.gamma.rounds]
+    return r
