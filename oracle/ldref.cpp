@@ -240,15 +240,18 @@ static double eval_raw(const double* g, int degree, int32_t x) {
     return r;
 }
 
-// s-basis coefficients -> raw-basis coefficients (reporting only; not used for decisions).
+// s-basis coefficients -> raw-basis coefficients (reporting only; not used for decisions):
+// the binomial expansion of c_p ((x - center) / 2^k)^p; C(p,q) and (-center)^(p-q) are
+// small integers, formed exactly by repeated multiplication.
 static void to_raw(const double* c, int degree, int32_t center, int32_t kshift, double* raw) {
     for (int q = 0; q <= degree; ++q) raw[q] = 0.0;
     for (int p = 0; p <= degree; ++p) {
         double cp = c[p] * std::ldexp(1.0, -kshift * p);
         double binom = 1.0;
         for (int q = 0; q <= p; ++q) {
-            // C(p,q) * (-center)^(p-q)
-            double term = cp * binom * std::pow(-(double)center, p - q);
+            double pw = 1.0;
+            for (int e = 0; e < p - q; ++e) pw = pw * -(double)center;
+            double term = cp * binom * pw;
             raw[q] += term;
             binom = binom * (double)(p - q) / (double)(q + 1);
         }
