@@ -1,0 +1,214 @@
+/* ld.h -- C ABI of the MI355X lane-detection library (libld.so).
+ *
+ * The library runs, on one AMD Instinct MI355X (gfx950), the per-frame hot path of the
+ * stereo lane detector of Fan & Dahnoun, "Real-Time Stereo Vision-Based Lane Detection
+ * System" (arXiv 1807.02752): from a left grey image and its disparity map to lane
+ * positions.  Every step runs in hand-written HIP kernels; nothing comes back to the host
+ * between steps.
+ *
+ * Conventions shared by every call
+ *  - Every function returns ld_status; no exception or abort crosses the ABI.
+ *  - Image buffers are DEVICE memory holding `batch` frames stacked vertically:
+ *    batch * height rows of `pitch` bytes each, frame b starting at row b * height.
+ *    Pixel (u, v) of frame b is at byte (b * height + v) * pitch + u * elem_size.
+ *  - Output buffers are DEVICE memory owned by the caller, unless stated otherwise.
+ *    Nullable outputs are skipped when NULL.
+ *  - Calls are asynchronous on `hip_stream` (a hipStream_t; NULL = the default stream).
+ *    Only argument checks are synchronous: a bad argument returns LD_E_INVAL and
+ *    enqueues nothing.  Inputs must stay alive until the enqueued work completes.
+ *  - A frame object (ld_frame) owns its device scratch and the state carried between
+ *    steps (road profile, V_p tables, edge lists, energies).  Use one host thread per
+ *    frame object at a time; calls on one frame object must use one stream, or the caller
+ *    must order the streams.
+ *  - Per-frame failures of the method are not errors: they are reported in
+ *    ld_lanes.flags (LD_FLAG_*) and as NaN rows of the V_p tables.
+ *  - Coordinates: u = column 0..width-1, v = row 0..height-1, v_max = height - 1.
+ */
+#ifndef LD_H
+#define LD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LD_OK = 0,
+    LD_E_INVAL = -1,   /* bad argument (null/unaligned pointer, size out of range, ...) */
+    LD_E_NOMEM = -2,   /* device scratch could not be allocated */
+    LD_E_HIP = -3,     /* a HIP runtime call failed (also deferred kernel errors, see ld_sync) */
+    LD_E_STATE = -4    /* a step was called before the step it depends on */
+} ld_status;
+
+/* Disparity pixel formats.  0 marks an invalid (rejected) pixel in every format; an F32
+ * pixel is also invalid if it is not finite or not positive. */
+typedef enum {
+    LD_DISP_U8 = 0,     /* uint8, disparity in px */
+    LD_DISP_F32 = 1,    /* float32, subpixel disparity in px */
+    LD_DISP_U16Q4 = 2   /* uint16, disparity in 1/16 px */
+} ld_disp_format;
+
+/* Per-frame flags reported in ld_lanes.flags. */
+enum {
+    LD_FLAG_NOROAD = 1,     /* no road profile could be fitted, or fewer than 8 road rows */
+    LD_FLAG_NOVP = 2,       /* the V_px fit failed */
+    LD_FLAG_NOCONS_Y = 4,   /* road-profile RANSAC ended without reaching the inlier fraction */
+    LD_FLAG_NOCONS_X = 8,   /* V_px RANSAC ended without reaching the inlier fraction */
+    LD_FLAG_FALLBACK = 16   /* the pruned search fell back to the full search */
+};
+
+#define LD_MAX_LANES 16
+
+/* Parameters of the method.  ld_params_default() fills the constants printed in the paper
+ * (Sec. 2.2-2.4) and the readings taken where it is silent. */
+typedef struct ld_params {
+    int32_t chi;           /* V_px band half-height, Sec. 2.3.2: 25 */
+    int32_t tau_y_max;     /* v-disparity DP jump bound, Eq. vpy_estimation: 6 */
+    int32_t tau_x_max;     /* V_px DP jump bound, Eq. dense_vpx_estimation: 5 (max 5) */
+    int32_t lambda_y;      /* DP smoothness weights (not given in the paper): 1, 1 */
+    int32_t lambda_x;
+    double tr_y;           /* RANSAC inlier tolerances, Sec. 2.2 and 2.3.3: 4, 16 */
+    double tr_x;
+    int32_t eps_num;       /* RANSAC exit fraction eps = eps_num / eps_den = 99/100 */
+    int32_t eps_den;
+    double varpi;          /* road tolerance |D - f(v)| <= varpi, Sec. 2.3.1: 3 */
+    int32_t edge_t;        /* Sobel magnitude threshold: 100 */
+    double sigma_g;        /* width of w_g, Eq. sigma_g: 3.5 */
+    int32_t nu;            /* M_0 box half-sizes (columns, rows), Sec. 2.4: 1, 3 (fixed) */
+    int32_t varsigma;
+    int32_t n_hyp;         /* RANSAC samples scored per round (not given): 64 (1..64) */
+    int32_t max_rounds;    /* RANSAC round cap (not given): 16 (1..64) */
+    double rho_lpv;        /* lane threshold: E < rho_lpv * min E (not given): 0.25 */
+    int32_t d_nms;         /* minimum lane separation in px; 0 -> max(8, width/64) */
+    int32_t weight_squared;/* 0: w_g exponent as printed; 1: squared (Gaussian) reading */
+    uint64_t seed;         /* Philox key word 0 of the RANSAC samples */
+} ld_params;
+
+/* Lanes of one frame.  u_start is the column of the lane on row v_max (it may lie outside
+ * the image: candidates span -width/2 .. 1.5*width), sorted ascending. */
+typedef struct ld_lanes {
+    int32_t n;                      /* number of lanes, 0..LD_MAX_LANES */
+    int32_t flags;                  /* LD_FLAG_* */
+    int32_t v_h;                    /* first road row (height if none) */
+    int32_t v_end;                  /* top row reached by the lane tracks */
+    int32_t u_start[LD_MAX_LANES];
+    float energy[LD_MAX_LANES];     /* candidate energy of each lane (negative) */
+} ld_lanes;
+
+typedef struct ld_frame_s* ld_frame;
+
+/* Fill p with the defaults described above. */
+void ld_params_default(ld_params* p);
+
+/* Create a frame object for `batch` frames of width x height pixels whose disparity is in
+ * format `fmt` with bins 0..d_max.  Limits: 8 <= width <= 4096, 8 <= height <= 4096,
+ * 1 <= batch <= 65535, 1 <= d_max <= 1023.  p may be NULL (defaults).  The scratch is
+ * allocated on the current HIP device (LD_E_NOMEM if it does not fit). */
+ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
+                          const ld_params* p, ld_frame* out);
+
+/* Free a frame object (synchronises its last stream first).  NULL is accepted. */
+ld_status ld_frame_destroy(ld_frame f);
+
+/* Process only the first n frames (1 <= n <= batch) in the following calls.  Default:
+ * batch. */
+ld_status ld_frame_set_active(ld_frame f, int32_t n);
+
+/* Step 1 (Sec. 2.2): v-disparity histogram, DP path on it, road profile beta by RANSAC
+ * (Alg. "beta estimation"), V_py(v) (Eq. vpy_equation) and the road rows.
+ *  disp, disp_pitch : disparity frames (see above), pitch >= width * elem_size.
+ *  stream_ids       : nullable device array of n uint64, Philox key word 1 per frame
+ *                     (NULL: 0).
+ *  frame_idx        : nullable device array of n int64, Philox counter word 0 per frame
+ *                     (NULL: the frame's index in the batch).
+ *  vdisp_out        : nullable device int32 n x height x (d_max+1), row-major m_y(v, d).
+ *  beta_out         : nullable device double n x 3, road profile f(v) = b0 + b1 v + b2 v^2
+ *                     (NaN if no fit). */
+ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint64_t* stream_ids,
+                   const int64_t* frame_idx, int32_t* vdisp_out, double* beta_out, void* hip_stream);
+
+/* Step 2 (Sec. 2.3): Sobel gradient on the road surface, sparse V_px votes
+ * (Eq. sparse_vpx_estimation), band accumulation (Alg. "Dense V_px accumulation"), DP path
+ * (Eq. dense_vpx_estimation) and V_px by RANSAC (Alg. "gamma estimation",
+ * Eq. vpx_estimation).  Needs a prior ld_vdisp on this frame object (else LD_E_STATE).
+ *  grey, grey_pitch : uint8 grey frames, pitch >= width.
+ *  disp, disp_pitch : the same disparity frames as given to ld_vdisp.
+ *  stream_ids, frame_idx : as in ld_vdisp (they key the V_px RANSAC samples).
+ *  seed_gamma       : nullable device double n x 5, a raw-basis quartic in v used as
+ *                     RANSAC hypothesis 0 (a learned or tracked seed).
+ *  vp_out           : nullable device double n x height x 2, (V_px, V_py) per row, NaN
+ *                     outside the road rows. */
+ld_status ld_vp_ransac(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
+                       const uint64_t* stream_ids, const int64_t* frame_idx, const double* seed_gamma,
+                       double* vp_out, void* hip_stream);
+
+/* Step 3 (Sec. 2.4): weights w_g (Eq. sigma_g), M_0, M_1 and the energy of every lane
+ * candidate (Eq. lane_energy along Eq. lane_visualisation).  Needs a prior ld_vp_ransac.
+ *  cand_mask  : nullable device uint8 n x (2*width); 0 prunes a candidate (its energy is
+ *               reported as 0 and it cannot be a lane).  NULL = the full search.
+ *  energy_out : nullable device float n x (2*width); candidate i starts at column
+ *               i - width/2 on row v_max. */
+ld_status ld_lane_energy(ld_frame f, const uint8_t* cand_mask, float* energy_out, void* hip_stream);
+
+/* Step 4 (Alg. "Lane position validation"): local minima of the energies, threshold and
+ * suppression of nearby weaker minima; lane curves by iterating Eq. lane_visualisation.
+ * Needs a prior ld_lane_energy.
+ *  lanes_out  : n ld_lanes, device or host-pinned memory (written by a kernel).
+ *  curves_out : nullable device float n x LD_MAX_LANES x height, u of each lane per row,
+ *               NaN outside [v_end, v_max]. */
+ld_status ld_peaks(ld_frame f, ld_lanes* lanes_out, float* curves_out, void* hip_stream);
+
+/* All steps in order: ld_vdisp + ld_vp_ransac + ld_lane_energy (full search) + ld_peaks. */
+ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
+                    const uint64_t* stream_ids, const int64_t* frame_idx, ld_lanes* lanes_out, float* curves_out,
+                    void* hip_stream);
+
+/* Wait for the frame object's last stream; a failure of enqueued work surfaces here as
+ * LD_E_HIP. */
+ld_status ld_sync(ld_frame f);
+
+/* Static description of a status code. */
+const char* ld_status_string(ld_status s);
+
+/* Introspection: copy one piece of the device state of frame `b` into `dst` (device or
+ * host memory, `bytes` bytes available), asynchronously on hip_stream.  Returns LD_E_INVAL
+ * if `bytes` is too small.  Layouts (per frame):
+ *   LD_STATE_INFO      int32[8]: flags, v_h, v_end, n_my, n_edges, n_votes, R, n_mx
+ *   LD_STATE_MY_PATH   int32[2 * (d_max+1)]: x (row v) then y (disparity d) of the n_my
+ *                      points of the v-disparity DP path that carry votes
+ *   LD_STATE_BETA      ld_fit (see below)
+ *   LD_STATE_GAMMA     ld_fit
+ *   LD_STATE_TABLES    double[6 * height]: f, f', V_py, V_px, A_v, B_v (one row each;
+ *                      A_v, B_v are the track coefficients u_v = B_v u_{v+1} + A_v)
+ *   LD_STATE_ROWCOUNT  int32[height]: road edges per row
+ *   LD_STATE_EDGES     ld_edge[height * width]: per-row edge buckets (row v at v * width)
+ *   LD_STATE_MX_PATH   int32[height]: DP column c_v (0..2W-1) on road rows, -1 elsewhere
+ *   LD_STATE_ENERGY    double[2 * width]
+ *   LD_STATE_TRACE     int32[2 * 3 * max_rounds]: per RANSAC round (best hypothesis,
+ *                      its inlier count, points in the round), beta then gamma */
+enum {
+    LD_STATE_INFO = 0, LD_STATE_MY_PATH = 1, LD_STATE_BETA = 2, LD_STATE_GAMMA = 3, LD_STATE_TABLES = 4,
+    LD_STATE_ROWCOUNT = 5, LD_STATE_EDGES = 6, LD_STATE_MX_PATH = 7, LD_STATE_ENERGY = 8, LD_STATE_TRACE = 9
+};
+
+/* A robust polynomial fit: coefficients in the variable s = (v - center) / 2^kshift, and
+ * the same polynomial in raw v (reporting). */
+typedef struct ld_fit {
+    int32_t ok, flags, center, kshift, rounds, n_survivors;
+    double coef[5];
+    double raw[5];
+} ld_fit;
+
+/* One road edge pixel: column, Sobel gradient and V_px vote column (0..2W-1, -1 none). */
+typedef struct ld_edge {
+    int16_t u, gx, gy, bin;
+} ld_edge;
+
+ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LD_H */

@@ -1,0 +1,1281 @@
+// ld.hip -- MI355X (gfx950) kernels and C ABI of the lane-detection hot path.
+//
+// Method: Fan & Dahnoun, "Real-Time Stereo Vision-Based Lane Detection System"
+// (arXiv 1807.02752), Sec. 2.2-2.4.  One launch of each kernel processes a whole batch of
+// frames; per-pixel steps are spread over many workgroups per frame, the serial steps
+// (dynamic programming, RANSAC, row sweeps) run one workgroup per frame out of LDS.
+//
+//   k_vdisp_hist   S1   v-disparity histogram (LDS bins, wave-aggregated atomics)
+//   k_vdisp_fit    S2-3 DP on the v-disparity map, RANSAC road profile, V_py, road rows
+//   k_edges        S4-5 Sobel on road rows, road mask, V_px vote column per edge
+//   k_vpx_fit      S6-8 sliding band accumulator, row DP, RANSAC V_px, track tables
+//   k_energy       S9-12 w_g, M_0, M_1 row ring, candidate-by-row energy accumulation
+//   k_peaks        S13  minima, threshold, suppression, lane curves
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "ld_device.h"
+
+using namespace ldk;
+
+namespace {
+
+struct FitRes {
+    int32_t ok, flags, center, kshift, rounds, n_surv;
+    double coef[5];
+    double raw[5];
+};
+static_assert(sizeof(FitRes) == sizeof(ld_fit), "FitRes must mirror ld_fit");
+
+struct FrameInfo {
+    int32_t flags, v_h, v_end, n_my, n_edges, n_votes, R, n_mx;
+};
+
+constexpr int kMaxRounds = 64;
+constexpr int kBig = 0x3FFFFFFF;
+
+// Device view of a frame object: sizes, parameters and the scratch carried between steps.
+struct Dev {
+    int W, H, D1, W2, half, fmt, d_max, B;
+    ld_params P;
+    int32_t* myT;       // B x D1 x H   v-disparity counts, transposed (m_y(d, .) contiguous)
+    uint8_t* back_y;    // B x D1 x H   v-disparity DP backtrace (tau)
+    int32_t* my_pts;    // B x 2 x D1   DP path points with votes: rows, then disparities
+    FitRes* fit;        // B x 2        beta, gamma
+    FrameInfo* info;    // B
+    double* tab;        // B x 6 x H    f, f', V_py, V_px, A_v, B_v
+    int32_t* rowcnt;    // B x H        road edges per row
+    ld_edge* edges;     // B x H x W    per-row edge buckets
+    int8_t* back_x;     // B x H x 2W   row-DP backtrace (tau)
+    int32_t* mxpath;    // B x H        row-DP path columns
+    double* energy;     // B x 2W
+    int32_t* trace;     // B x 2 x 3 x kMaxRounds
+};
+
+// ------------------------------------------------------------------------------------------
+// Block-wide helpers (256 threads)
+__device__ __forceinline__ int block_max_i32(int x, int* red) {
+    x = wave_max_i32(x);
+    int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = x;
+    __syncthreads();
+    int r = red[0];
+    for (int i = 1; i < kWaves; ++i) r = max(r, red[i]);
+    return r;
+}
+
+__device__ __forceinline__ int block_min_i32(int x, int* red) {
+    x = wave_min_i32(x);
+    int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = x;
+    __syncthreads();
+    int r = red[0];
+    for (int i = 1; i < kWaves; ++i) r = min(r, red[i]);
+    return r;
+}
+
+__device__ __forceinline__ int block_sum_i32(int x, int* red) {
+    x = wave_sum_i32(x);
+    int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) red[w] = x;
+    __syncthreads();
+    int r = 0;
+    for (int i = 0; i < kWaves; ++i) r += red[i];
+    return r;
+}
+
+// (value, index) argmin over the block, ties to the smaller index
+__device__ __forceinline__ void block_argmin_i64(int64_t& v, int& i, int64_t* rv, int* ri) {
+    wave_argmin_i64(v, i);
+    int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane_id() == 0) { rv[w] = v; ri[w] = i; }
+    __syncthreads();
+    v = rv[0];
+    i = ri[0];
+    for (int k = 1; k < kWaves; ++k)
+        if (rv[k] < v || (rv[k] == v && ri[k] < i)) { v = rv[k]; i = ri[k]; }
+}
+
+// ------------------------------------------------------------------------------------------
+// RANSAC (Alg. "beta/gamma estimation with the assist of RANSAC").  Each round scores up to
+// 64 random samples of DEG+1 points, one per lane of wave 0, and the points are split over
+// the four waves for the inlier count; the best sample's outliers are removed by a stable
+// ballot compaction; the loop ends when the inliers reach eps of the round's points.  The
+// final model is refitted on the survivors from exact 128-bit moments.
+struct RansacShared {
+    double models[kMaxHyp][5];
+    int mvalid[kMaxHyp];            // 0 invalid, 1 fitted (s basis), 2 caller seed (raw basis)
+    int counts[kWaves][kMaxHyp];
+    int wsum[kWaves];
+    int red[kWaves];
+    int best_h, best_n;
+    i128 mred[kWaves][14];
+};
+
+template <int DEG>
+__device__ __forceinline__ bool is_inlier(const double* m, int kind, int center, int kshift, int x, int y,
+                                          double tr) {
+    double fv = (kind == 2) ? eval_raw<DEG>(m, x) : eval_s<DEG>(m, center, kshift, x);
+    double res = (double)y - fv;
+    return res * res < tr;
+}
+
+template <int DEG>
+__device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* cur2, uint32_t* bitmap,
+                             int bitmap_words, RansacShared& S, double tr, const ld_params& P, uint64_t key1,
+                             uint64_t ctr0, int stage, const double* seed_raw, FitRes* out, int* trace) {
+    constexpr int s = DEG + 1;
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    FitRes res;
+    res.ok = 0; res.flags = 0; res.center = 0; res.kshift = 0; res.rounds = 0; res.n_surv = 0;
+    for (int p = 0; p < 5; ++p) { res.coef[p] = 0.0; res.raw[p] = 0.0; }
+    if (n0 < s) {
+        if (t == 0) { res.flags = 1; *out = res; }
+        __syncthreads();
+        return;
+    }
+    int xmn = 0x7fffffff, xmx = -0x7fffffff;
+    for (int j = t; j < n0; j += kBlock) { xmn = min(xmn, X[j]); xmx = max(xmx, X[j]); }
+    xmn = block_min_i32(xmn, S.red);
+    xmx = block_max_i32(xmx, S.red);
+    const int center = (xmn + xmx) >> 1;
+    const int wmax = max(xmx - center, center - xmn);
+    int k = 0;
+    while ((1 << k) < wmax) ++k;
+    res.center = center;
+    res.kshift = k;
+    for (int j = t; j < n0; j += kBlock) cur[j] = j;
+    const int need = max(s, (n0 + 9) / 10);
+    const int n_hyp = min(P.n_hyp, kMaxHyp);
+    int n_cur = n0;
+    bool converged = false;
+    int r = 0;
+    __syncthreads();
+    for (; r < P.max_rounds; ++r) {
+        // ---- phase A: one sample + fit per hypothesis (wave 0)
+        if (t < n_hyp) {
+            double model[5] = {0, 0, 0, 0, 0};
+            int kind = 0;
+            if (t == 0 && seed_raw != nullptr) {
+                for (int p = 0; p <= DEG; ++p) model[p] = seed_raw[p];
+                kind = 2;
+            } else {
+                int pick[s];
+                int got = 0;
+                for (int blk = 0; blk < 16 && got < s; ++blk) {
+                    U64x4 w = philox4x64_10(ctr0, ((uint64_t)stage << 32) | (uint64_t)(uint32_t)r, (uint64_t)t,
+                                            (uint64_t)blk, P.seed, key1);
+                    for (int q = 0; q < 4 && got < s; ++q) {
+                        int ix = (int)__umul64hi(w.w[q], (uint64_t)n_cur);
+                        bool dup = false;
+                        for (int e = 0; e < got; ++e) dup = dup || (pick[e] == ix);
+                        if (!dup) pick[got++] = ix;
+                    }
+                }
+                if (got == s) {
+                    int distinct = 0;
+                    for (int e = 0; e < s; ++e) {
+                        bool seen = false;
+                        for (int f = 0; f < e; ++f) seen = seen || (X[cur[pick[f]]] == X[cur[pick[e]]]);
+                        distinct += seen ? 0 : 1;
+                    }
+                    if (distinct == s) {
+                        Moments M;
+                        moments_zero(M);
+                        for (int e = 0; e < s; ++e) moments_add<DEG>(M, X[cur[pick[e]]], Y[cur[pick[e]]], center);
+                        kind = solve_moments<DEG>(M, k, model) ? 1 : 0;
+                    }
+                }
+            }
+            for (int p = 0; p < 5; ++p) S.models[t][p] = model[p];
+            S.mvalid[t] = kind;
+        }
+        __syncthreads();
+        // ---- phase B: inlier counts, hypothesis = lane, points split over the waves
+        {
+            const int h = lane;
+            int cnt = -1;
+            if (h < n_hyp && S.mvalid[h] != 0) {
+                cnt = 0;
+                const double* m = S.models[h];
+                const int kind = S.mvalid[h];
+                for (int jj = wave; jj < n_cur; jj += kWaves) {
+                    int j = cur[jj];
+                    cnt += is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr) ? 1 : 0;
+                }
+            }
+            S.counts[wave][h] = cnt;
+        }
+        __syncthreads();
+        // ---- phase C: best hypothesis (most inliers, lowest index)
+        if (wave == 0) {
+            int tot = -1;
+            if (lane < n_hyp && S.counts[0][lane] >= 0) {
+                tot = 0;
+                for (int w = 0; w < kWaves; ++w) tot += S.counts[w][lane];
+            }
+            int bn = tot, bh = lane;
+            for (int o = 32; o > 0; o >>= 1) {
+                int on = __shfl_xor(bn, o, kWave), oh = __shfl_xor(bh, o, kWave);
+                if (on > bn || (on == bn && oh < bh)) { bn = on; bh = oh; }
+            }
+            if (lane == 0) { S.best_h = bn >= 0 ? bh : -1; S.best_n = bn; }
+        }
+        __syncthreads();
+        const int best_h = S.best_h, best_n = S.best_n;
+        if (trace && t == 0) { trace[3 * r] = best_h; trace[3 * r + 1] = best_n; trace[3 * r + 2] = n_cur; }
+        if (best_h < 0 || best_n < need) { ++r; break; }
+        // ---- phase D: keep the inliers of the best sample, in order
+        {
+            const double* m = S.models[best_h];
+            const int kind = S.mvalid[best_h];
+            int base = 0;
+            for (int c0 = 0; c0 < n_cur; c0 += kBlock) {
+                int jj = c0 + t, j = 0;
+                bool pred = false;
+                if (jj < n_cur) {
+                    j = cur[jj];
+                    pred = is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr);
+                }
+                uint64_t bal = __ballot(pred);
+                int wpre = __popcll(bal & lanes_below());
+                if (lane == 0) S.wsum[wave] = __popcll(bal);
+                __syncthreads();
+                int off = base, tot = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    if (w < wave) off += S.wsum[w];
+                    tot += S.wsum[w];
+                }
+                if (pred) cur2[off + wpre] = j;
+                base += tot;
+                __syncthreads();
+            }
+        }
+        const bool done = (int64_t)P.eps_den * best_n >= (int64_t)P.eps_num * n_cur;
+        int* tmp = cur; cur = cur2; cur2 = tmp;
+        n_cur = best_n;
+        __syncthreads();
+        if (done) { converged = true; ++r; break; }
+    }
+    res.rounds = r;
+    res.flags = converged ? 0 : 1;
+    res.n_surv = n_cur;
+    // ---- final fit on the survivors: distinct abscissae, exact moments, solve
+    for (int i = t; i < bitmap_words; i += kBlock) bitmap[i] = 0u;
+    __syncthreads();
+    for (int jj = t; jj < n_cur; jj += kBlock) {
+        int x = X[cur[jj]];
+        atomicOr(&bitmap[x >> 5], 1u << (x & 31));
+    }
+    __syncthreads();
+    int pc = 0;
+    for (int i = t; i < bitmap_words; i += kBlock) pc += __popc(bitmap[i]);
+    const int distinct = block_sum_i32(pc, S.red);
+    Moments M;
+    moments_zero(M);
+    for (int jj = t; jj < n_cur; jj += kBlock) moments_add<DEG>(M, X[cur[jj]], Y[cur[jj]], center);
+    for (int p = 0; p <= 2 * DEG; ++p) M.sw[p] = wave_sum_i128(M.sw[p]);
+    for (int p = 0; p <= DEG; ++p) M.syw[p] = wave_sum_i128(M.syw[p]);
+    if (lane == 0) {
+        for (int p = 0; p <= 2 * DEG; ++p) S.mred[wave][p] = M.sw[p];
+        for (int p = 0; p <= DEG; ++p) S.mred[wave][9 + p] = M.syw[p];
+    }
+    __syncthreads();
+    if (t == 0) {
+        if (distinct >= s) {
+            Moments T;
+            moments_zero(T);
+            for (int w = 0; w < kWaves; ++w) {
+                for (int p = 0; p <= 2 * DEG; ++p) T.sw[p] += S.mred[w][p];
+                for (int p = 0; p <= DEG; ++p) T.syw[p] += S.mred[w][9 + p];
+            }
+            if (solve_moments<DEG>(T, k, res.coef)) {
+                res.ok = 1;
+                to_raw<DEG>(res.coef, center, k, res.raw);
+            }
+        }
+        *out = res;
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------
+// S1: v-disparity histogram m_y(d, v) (Sec. 2.2).  A workgroup bins kHistRows rows of one
+// frame into LDS; within a wave, lanes with the same bin are merged by ballot before one LDS
+// atomic (a road row puts most pixels into one or two bins).
+constexpr int kHistRows = 4;
+
+template <int FMT>
+__device__ __forceinline__ bool disp_bin(const uint8_t* row, int u, int d_max, int& bin) {
+    if (FMT == LD_DISP_U8) {
+        int r = row[u];
+        bin = min(r, d_max);
+        return r != 0;
+    } else if (FMT == LD_DISP_F32) {
+        float x = reinterpret_cast<const float*>(row)[u];
+        if (!(isfinite(x) && x > 0.0f)) return false;
+        double b = floor((double)x + 0.5);
+        bin = b > (double)d_max ? d_max : (int)b;
+        return true;
+    } else {
+        int r = reinterpret_cast<const uint16_t*>(row)[u];
+        bin = min((r + 8) >> 4, d_max);
+        return r != 0;
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* disp, int64_t pitch, int32_t* vdisp_out) {
+    extern __shared__ int hist[];   // kHistRows x D1
+    const int b = blockIdx.y, v0 = blockIdx.x * kHistRows, t = threadIdx.x, lane = lane_id();
+    const int D1 = d.D1, W = d.W, H = d.H;
+    for (int i = t; i < kHistRows * D1; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    for (int r = 0; r < kHistRows; ++r) {
+        const int v = v0 + r;
+        if (v >= H) break;
+        const uint8_t* row = disp + ((int64_t)b * H + v) * pitch;
+        for (int u0 = 0; u0 < W; u0 += kBlock) {
+            const int u = u0 + t;
+            int bin = 0;
+            bool valid = (u < W) && disp_bin<FMT>(row, u, d.d_max, bin);
+            uint64_t act = __ballot(valid);
+            while (act) {
+                const int leader = __ffsll((unsigned long long)act) - 1;
+                const int b0 = __shfl(bin, leader, kWave);
+                const bool same = valid && bin == b0;
+                const uint64_t m = __ballot(same);
+                if (lane == leader) atomicAdd(&hist[r * D1 + b0], __popcll(m));
+                if (same) valid = false;
+                act &= ~m;
+            }
+        }
+    }
+    __syncthreads();
+    const int rows = min(kHistRows, H - v0);
+    for (int i = t; i < rows * D1; i += kBlock) {
+        const int dd = i / rows, r = i % rows;
+        d.myT[((int64_t)b * D1 + dd) * H + v0 + r] = hist[r * D1 + dd];
+    }
+    if (vdisp_out) {
+        for (int i = t; i < rows * D1; i += kBlock) {
+            const int r = i / D1, dd = i % D1;
+            vdisp_out[((int64_t)b * H + v0 + r) * D1 + dd] = hist[r * D1 + dd];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// S2 + S3: DP on the v-disparity map (Eq. vpy_estimation), RANSAC road profile beta
+// (Alg. "beta estimation"), tables f, f', V_py (Eq. vpy_equation) and the road rows.  One
+// workgroup per frame; E lives in two LDS rows, the backtrace in global memory.
+__global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                      double* beta_out) {
+    extern __shared__ unsigned char smem[];
+    __shared__ RansacShared S;
+    __shared__ int64_t rv[kWaves];
+    __shared__ int ri[kWaves];
+    __shared__ int s_n;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int H = d.H, D1 = d.D1, d_max = d.d_max;
+    int* E0 = reinterpret_cast<int*>(smem);
+    int* E1 = E0 + H;
+    int* PX = E1 + H;
+    int* PY = PX + D1;
+    int* cur = PY + D1;
+    int* cur2 = cur + D1;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + D1);
+    const int bm_words = (H + 31) / 32;
+    const int32_t* myT = d.myT + (int64_t)b * D1 * H;
+    uint8_t* back = d.back_y + (int64_t)b * D1 * H;
+    const int tau_max = d.P.tau_y_max, lam = d.P.lambda_y;
+
+    for (int v = t; v < H; v += kBlock) {
+        E0[v] = -myT[(int64_t)d_max * H + v];
+        d.rowcnt[(int64_t)b * H + v] = 0;
+    }
+    __syncthreads();
+    int* Ec = E0;
+    int* En = E1;
+    for (int dd = d_max - 1; dd >= 0; --dd) {
+        for (int v = t; v < H; v += kBlock) {
+            int best = Ec[v], bt = 0;
+            for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
+                int c = Ec[v + tau] + lam * tau;
+                if (c < best) { best = c; bt = tau; }
+            }
+            En[v] = -myT[(int64_t)dd * H + v] + best;
+            back[(int64_t)dd * H + v] = (uint8_t)bt;
+        }
+        __syncthreads();
+        int* tmp = Ec; Ec = En; En = tmp;
+    }
+    int64_t bv = INT64_MAX;
+    int bi = 0x7fffffff;
+    for (int v = t; v < H; v += kBlock)
+        if ((int64_t)Ec[v] < bv) { bv = Ec[v]; bi = v; }
+    block_argmin_i64(bv, bi, rv, ri);
+    if (t == 0) {
+        int v = bi, n = 0;
+        for (int dd = 0; dd <= d_max; ++dd) {
+            if (myT[(int64_t)dd * H + v] > 0) { PX[n] = v; PY[n] = dd; ++n; }
+            if (dd < d_max) v += back[(int64_t)dd * H + v];
+        }
+        s_n = n;
+    }
+    __syncthreads();
+    const int n_my = s_n;
+    for (int i = t; i < n_my; i += kBlock) {
+        d.my_pts[(int64_t)b * 2 * D1 + i] = PX[i];
+        d.my_pts[(int64_t)b * 2 * D1 + D1 + i] = PY[i];
+    }
+    const uint64_t sid = stream_ids ? stream_ids[b] : 0ull;
+    const uint64_t fid = frame_idx ? (uint64_t)frame_idx[b] : (uint64_t)b;
+    FitRes* fit = d.fit + 2 * b;
+    ransac_block<2>(PX, PY, n_my, cur, cur2, bitmap, bm_words, S, d.P.tr_y, d.P, sid, fid, 0, nullptr, fit,
+                    d.trace + (int64_t)b * 6 * kMaxRounds);
+    // tables and road rows
+    const FitRes& beta = *fit;
+    const int ok = beta.ok;
+    double* tf = d.tab + (int64_t)b * 6 * H;
+    double* tfp = tf + H;
+    double* tvpy = tf + 2 * H;
+    double* tvpx = tf + 3 * H;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    int bad = -1;
+    if (ok) {
+        const double sc = ldexp(1.0, -beta.kshift);
+        for (int v = t; v < H; v += kBlock) {
+            double s = (double)(v - beta.center) * sc;
+            double fv = beta.coef[2];
+            fv = fv * s + beta.coef[1];
+            fv = fv * s + beta.coef[0];
+            double tt = 2.0 * beta.coef[2];
+            double dv = (beta.coef[1] + tt * s) * sc;
+            tf[v] = fv;
+            tfp[v] = dv;
+            tvpy[v] = (double)v - fv / dv;
+            tvpx[v] = nan;
+            if (!(fv > 0.0 && dv > 0.0)) bad = max(bad, v);
+        }
+    } else {
+        for (int v = t; v < H; v += kBlock) { tf[v] = nan; tfp[v] = nan; tvpy[v] = nan; tvpx[v] = nan; }
+    }
+    bad = block_max_i32(bad, S.red);
+    if (t == 0) {
+        FrameInfo fi;
+        fi.flags = (beta.flags & 1) ? LD_FLAG_NOCONS_Y : 0;
+        fi.v_h = ok ? bad + 1 : H;
+        fi.R = H - fi.v_h;
+        if (!ok || fi.R < 8) fi.flags |= LD_FLAG_NOROAD;
+        fi.v_end = H;
+        fi.n_my = n_my;
+        fi.n_edges = 0;
+        fi.n_votes = 0;
+        fi.n_mx = 0;
+        d.info[b] = fi;
+        if (beta_out) {
+            for (int p = 0; p < 3; ++p) beta_out[3 * b + p] = ok ? beta.raw[p] : nan;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// S4 + S5: Sobel gradient on the road rows, road mask (Sec. 2.3.1), edge test, and the V_px
+// vote of every road edge (Eq. sparse_vpx_estimation with the gradient read as the edge
+// slope).  A workgroup covers kBlock columns x kEdgeRows rows; edges are appended to their
+// row's bucket with one atomic per wave.
+constexpr int kEdgeRows = 8;
+
+template <int FMT>
+__device__ __forceinline__ bool disp_value(const uint8_t* row, int u, double& D) {
+    if (FMT == LD_DISP_U8) {
+        int r = row[u];
+        D = (double)r;
+        return r != 0;
+    } else if (FMT == LD_DISP_F32) {
+        float x = reinterpret_cast<const float*>(row)[u];
+        D = (double)x;
+        return isfinite(x) && x > 0.0f;
+    } else {
+        int r = reinterpret_cast<const uint16_t*>(row)[u];
+        D = (double)r / 16.0;
+        return r != 0;
+    }
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
+                                                  int64_t dpitch) {
+    const int b = blockIdx.z, v0 = blockIdx.y * kEdgeRows, u = blockIdx.x * kBlock + threadIdx.x;
+    const int W = d.W, H = d.H, lane = lane_id();
+    const FrameInfo fi = d.info[b];
+    if (fi.flags & LD_FLAG_NOROAD) return;
+    if (v0 + kEdgeRows <= fi.v_h) return;
+    const double* tf = d.tab + (int64_t)b * 6 * H;
+    const double* tvpy = tf + 2 * H;
+    const int64_t t2 = (int64_t)d.P.edge_t * d.P.edge_t;
+    const double varpi = d.P.varpi;
+    for (int r = 0; r < kEdgeRows; ++r) {
+        const int v = v0 + r;
+        if (v < fi.v_h || v >= H) continue;
+        bool edge = false;
+        int gx = 0, gy = 0, bin = -1;
+        if (u < W) {
+            double D;
+            const uint8_t* drow = disp + ((int64_t)b * H + v) * dpitch;
+            if (disp_value<FMT>(drow, u, D) && fabs(D - tf[v]) <= varpi && u >= 1 && u <= W - 2 && v >= 1 &&
+                v <= H - 2) {
+                const uint8_t* g0 = grey + ((int64_t)b * H + v - 1) * gpitch;
+                const uint8_t* g1 = g0 + gpitch;
+                const uint8_t* g2 = g1 + gpitch;
+                const int a0 = g0[u - 1], a1 = g0[u], a2 = g0[u + 1];
+                const int b0 = g1[u - 1], b2 = g1[u + 1];
+                const int c0 = g2[u - 1], c1 = g2[u], c2 = g2[u + 1];
+                gx = (a2 - a0) + 2 * (b2 - b0) + (c2 - c0);
+                gy = (c0 - a0) + 2 * (c1 - a1) + (c2 - a2);
+                edge = (int64_t)gx * gx + (int64_t)gy * gy > t2;
+                if (edge && gx != 0) {
+                    double tt = (double)v - tvpy[v];
+                    double x = (double)u + (tt * (double)gy) / (double)gx;
+                    double bf = floor(x + 0.5);
+                    if (bf >= -(double)d.half && bf < (double)(d.W2 - d.half)) bin = (int)bf + d.half;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(edge);
+        if (bal) {
+            const int leader = __ffsll((unsigned long long)bal) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], __popcll(bal));
+            base = __shfl(base, leader, kWave);
+            if (edge) {
+                ld_edge e;
+                e.u = (int16_t)u; e.gx = (int16_t)gx; e.gy = (int16_t)gy; e.bin = (int16_t)bin;
+                d.edges[((int64_t)b * H + v) * W + base + __popcll(bal & lanes_below())] = e;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// S6 + S7 + S8: band accumulator m_x (Alg. "Dense V_px accumulation", a band of 2 chi + 1 rows
+// clipped to the road), DP path over the 2W vote columns (Eq. dense_vpx_estimation), RANSAC
+// quartic gamma (Alg. "gamma estimation"), V_px table (Eq. vpx_estimation) and the
+// coefficients of the lane track of Eq. lane_visualisation.  One workgroup per frame: the
+// band histogram and two padded DP rows live in LDS, the backtrace in global memory.
+__device__ __forceinline__ void band_row(const Dev& d, int b, int v, int sign, int* hist) {
+    const int cnt = d.rowcnt[(int64_t)b * d.H + v];
+    const ld_edge* e = d.edges + ((int64_t)b * d.H + v) * d.W;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+        const int bin = e[i].bin;
+        if (bin >= 0) atomicAdd(&hist[bin], sign);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                    const double* seed_gamma, double* vp_out) {
+    extern __shared__ unsigned char smem[];
+    __shared__ RansacShared S;
+    __shared__ int64_t rv[kWaves];
+    __shared__ int ri[kWaves];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int H = d.H, W2 = d.W2, v_max = H - 1;
+    FrameInfo fi = d.info[b];
+    double* tf = d.tab + (int64_t)b * 6 * H;
+    double* tvpy = tf + 2 * H;
+    double* tvpx = tf + 3 * H;
+    double* tA = tf + 4 * H;
+    double* tB = tf + 5 * H;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int v = t; v < H; v += kBlock) {
+        tA[v] = 0.0;
+        tB[v] = 0.0;
+        d.mxpath[(int64_t)b * H + v] = -1;
+    }
+    if (fi.flags & LD_FLAG_NOROAD) {
+        if (vp_out)
+            for (int v = t; v < H; v += kBlock) {
+                vp_out[((int64_t)b * H + v) * 2] = nan;
+                vp_out[((int64_t)b * H + v) * 2 + 1] = nan;
+            }
+        return;
+    }
+    const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
+    int* hist = reinterpret_cast<int*>(smem);
+    int* Ea = hist + W2;            // padded by 5 on each side
+    int* Eb = Ea + W2 + 10;
+    int* PX = Eb + W2 + 10;
+    int* PY = PX + H;
+    int* cur = PY + H;
+    int* cur2 = cur + H;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + H);
+    const int bm_words = (H + 31) / 32;
+    // edge and vote totals
+    int ne = 0, nv = 0;
+    for (int v = v_h; v <= v_max; ++v) ne += d.rowcnt[(int64_t)b * H + v];
+    for (int v = v_h; v <= v_max; ++v) {
+        const int cnt = d.rowcnt[(int64_t)b * H + v];
+        const ld_edge* e = d.edges + ((int64_t)b * H + v) * d.W;
+        for (int i = t; i < cnt; i += kBlock) nv += e[i].bin >= 0 ? 1 : 0;
+    }
+    nv = block_sum_i32(nv, S.red);
+    for (int c = t; c < W2; c += kBlock) hist[c] = 0;
+    for (int c = t; c < 5; c += kBlock) {
+        Ea[c] = kBig; Ea[W2 + 5 + c] = kBig;
+        Eb[c] = kBig; Eb[W2 + 5 + c] = kBig;
+    }
+    __syncthreads();
+    for (int v = max(v_max - chi, v_h); v <= v_max; ++v) band_row(d, b, v, 1, hist);
+    __syncthreads();
+    int* Ec = Ea + 5;
+    int* En = Eb + 5;
+    for (int c = t; c < W2; c += kBlock) Ec[c] = -hist[c];
+    __syncthreads();
+    const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
+    int8_t* back = d.back_x + (int64_t)b * H * W2;
+    for (int v = v_max - 1; v >= v_h; --v) {
+        if (v - chi >= v_h) band_row(d, b, v - chi, 1, hist);
+        if (v + chi + 1 <= v_max) band_row(d, b, v + chi + 1, -1, hist);
+        __syncthreads();
+        for (int c = t; c < W2; c += kBlock) {
+            int best = Ec[c], bt = 0;
+            for (int a = 1; a <= tau_max; ++a) {
+                const int vl = Ec[c - a] + lam * a;
+                if (vl < best) { best = vl; bt = -a; }
+                const int vr = Ec[c + a] + lam * a;
+                if (vr < best) { best = vr; bt = a; }
+            }
+            En[c] = -hist[c] + best;
+            back[(int64_t)v * W2 + c] = (int8_t)bt;
+        }
+        __syncthreads();
+        int* tmp = Ec; Ec = En; En = tmp;
+    }
+    int64_t bvv = INT64_MAX;
+    int bi = 0x7fffffff;
+    for (int c = t; c < W2; c += kBlock)
+        if ((int64_t)Ec[c] < bvv) { bvv = Ec[c]; bi = c; }
+    block_argmin_i64(bvv, bi, rv, ri);
+    if (t == 0) {
+        int c = bi;
+        for (int v = v_h; v <= v_max; ++v) {
+            d.mxpath[(int64_t)b * H + v] = c;
+            PX[v - v_h] = v;
+            PY[v - v_h] = c - d.half;
+            if (v < v_max) c += back[(int64_t)v * W2 + c];
+        }
+    }
+    __syncthreads();
+    const uint64_t sid = stream_ids ? stream_ids[b] : 0ull;
+    const uint64_t fid = frame_idx ? (uint64_t)frame_idx[b] : (uint64_t)b;
+    FitRes* fit = d.fit + 2 * b + 1;
+    ransac_block<4>(PX, PY, R, cur, cur2, bitmap, bm_words, S, d.P.tr_x, d.P, sid, fid, 1,
+                    seed_gamma ? seed_gamma + 5 * (int64_t)b : nullptr, fit,
+                    d.trace + (int64_t)b * 6 * kMaxRounds + 3 * kMaxRounds);
+    const FitRes& g = *fit;
+    int bad = v_h - 1;
+    if (g.ok) {
+        for (int v = t; v < H; v += kBlock)
+            tvpx[v] = (v >= v_h) ? eval_s<4>(g.coef, g.center, g.kshift, v) : nan;
+    }
+    __syncthreads();
+    if (g.ok) {
+        for (int v = v_h + t; v <= v_max - 1; v += kBlock) {
+            const double den = (double)(v + 1) - tvpy[v + 1];
+            if (!(den > 0.0)) {
+                bad = max(bad, v);
+            } else {
+                tA[v] = tvpx[v + 1] / den;
+                tB[v] = ((double)v - tvpy[v + 1]) / den;
+            }
+        }
+    }
+    bad = block_max_i32(bad, S.red);
+    if (t == 0) {
+        fi.flags |= (g.flags & 1) ? LD_FLAG_NOCONS_X : 0;
+        if (!g.ok) fi.flags |= LD_FLAG_NOVP;
+        fi.v_end = g.ok ? bad + 1 : H;
+        fi.n_edges = ne;
+        fi.n_votes = nv;
+        fi.n_mx = R;
+        d.info[b] = fi;
+    }
+    if (vp_out) {
+        for (int v = t; v < H; v += kBlock) {
+            const bool road = v >= v_h && g.ok;
+            vp_out[((int64_t)b * H + v) * 2] = road ? tvpx[v] : nan;
+            vp_out[((int64_t)b * H + v) * 2 + 1] = v >= v_h ? tvpy[v] : nan;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// S9 - S12: piecewise weight w_g (Eq. sigma_g), q = G_x w_g, M_0 (box of 3 columns x 7 rows)
+// and M_1 = Sobel-x of M_0 (Alg. "Lane position validation"), and the energy of every
+// candidate along its track (Eq. lane_energy, Eq. lane_visualisation).  One workgroup per
+// frame sweeps the road rows upwards: the q rows of the 7-row box are kept per thread in
+// registers for the NC columns it owns; C (vertical 7-sums), a 3-row M_0 ring and the M_1 row
+// are in LDS.  Each thread carries NT candidates' track position (FP64) and energy.
+__device__ __forceinline__ int mod3(int x) { return ((x % 3) + 3) % 3; }
+
+template <int NC, int NT>
+__global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_mask, float* energy_out) {
+    extern __shared__ float fsm[];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int W = d.W, H = d.H, W2 = d.W2, v_max = H - 1;
+    const FrameInfo fi = d.info[b];
+    double* Eout = d.energy + (int64_t)b * W2;
+    if (fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP)) {
+        for (int i = t; i < W2; i += kBlock) {
+            Eout[i] = 0.0;
+            if (energy_out) energy_out[(int64_t)b * W2 + i] = 0.0f;
+        }
+        return;
+    }
+    float* qrow = fsm;               // W
+    float* Crow = qrow + W;          // W
+    float* M0 = Crow + W;            // 3 x W ring
+    float* M1 = M0 + 3 * W;          // W
+    const double* tf = d.tab + (int64_t)b * 6 * H;
+    const double* tvpy = tf + 2 * H;
+    const double* tvpx = tf + 3 * H;
+    const double* tA = tf + 4 * H;
+    const double* tB = tf + 5 * H;
+    const int v_h = fi.v_h, v_end = fi.v_end;
+    const double theta_s = 3.14159265358979323846 / 36.0;
+    const float inv_sg2 = (float)(1.0 / (d.P.sigma_g * d.P.sigma_g));
+    const int sq = d.P.weight_squared;
+
+    float ring[NC][7];
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) ring[k][j] = 0.0f;
+    double uu[NT], ee[NT];
+    bool live[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int i = t + k * kBlock;
+        uu[k] = (double)(i - d.half);
+        ee[k] = 0.0;
+        live[k] = i < W2 && (cand_mask == nullptr || cand_mask[(int64_t)b * W2 + i] != 0);
+    }
+    for (int i = t; i < 3 * W; i += kBlock) M0[i] = 0.0f;
+
+    // q row r: zero, then scatter the weighted edges of that row
+    auto load_q_row = [&](int r) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int u = t + k * kBlock;
+            if (u < W) qrow[u] = 0.0f;
+        }
+        __syncthreads();
+        if (r >= v_h && r <= v_max) {
+            const int cnt = d.rowcnt[(int64_t)b * H + r];
+            const ld_edge* e = d.edges + ((int64_t)b * H + r) * W;
+            const double vx = tvpx[r], vy = tvpy[r];
+            for (int i = t; i < cnt; i += kBlock) {
+                const ld_edge ed = e[i];
+                const double tx = (double)(-ed.gy), ty = (double)ed.gx;
+                const double rx = vx - (double)ed.u, ry = vy - (double)r;
+                const double dot = tx * rx + ty * ry;
+                const double tt = tx * tx + ty * ty;
+                const double rr = rx * rx + ry * ry;
+                float q = 0.0f;
+                if (dot * dot >= (0.75 * tt) * rr) {
+                    const double cr = tx * ry - ty * rx;
+                    const float delta = atan2f((float)fabs(cr), (float)fabs(dot));
+                    const float p = delta / (float)theta_s;
+                    const float w = sq ? expf(-(p * p) * inv_sg2) : expf(-p * inv_sg2);
+                    q = (float)ed.gx * w;
+                }
+                qrow[ed.u] = q;
+            }
+        }
+        __syncthreads();
+    };
+    // push q row into the register ring (slot 0 = newest = lowest row)
+    auto push_ring = [&]() {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int u = t + k * kBlock;
+#pragma unroll
+            for (int j = 6; j > 0; --j) ring[k][j] = ring[k][j - 1];
+            ring[k][0] = (u < W) ? qrow[u] : 0.0f;
+        }
+    };
+    // preload q rows v_max, v_max-1, v_max-2 (rows below the image are zero)
+    for (int r = v_max; r >= v_max - 2; --r) {
+        load_q_row(r);
+        push_ring();
+    }
+    for (int m = v_max; m >= v_end - 1; --m) {
+        // q row m-3 enters; the ring then holds q rows m-3 .. m+3
+        load_q_row(m - 3);
+        push_ring();
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int u = t + k * kBlock;
+            if (u < W) {
+                float c = ring[k][0];
+#pragma unroll
+                for (int j = 1; j < 7; ++j) c += ring[k][j];
+                Crow[u] = c;
+            }
+        }
+        __syncthreads();
+        float* M0m = M0 + mod3(m) * W;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int u = t + k * kBlock;
+            if (u < W) {
+                const float l = u > 0 ? Crow[u - 1] : 0.0f;
+                const float rr = u < W - 1 ? Crow[u + 1] : 0.0f;
+                M0m[u] = (m >= 0 && m <= v_max) ? (l + Crow[u]) + rr : 0.0f;   // zero outside the image
+            }
+        }
+        __syncthreads();
+        const int kr = m + 1;   // M_1 row
+        if (kr <= v_max) {
+            const float* Ma = M0 + mod3(kr - 1) * W;                  // row kr-1 (= m)
+            const float* Mb = M0 + mod3(kr) * W;                      // row kr
+            const bool has_c = kr + 1 <= v_max;
+            const float* Mc = M0 + mod3(kr + 1) * W;                  // row kr+1
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const int u = t + k * kBlock;
+                if (u < W) {
+                    float ra = 0.0f, rb = 0.0f, rc = 0.0f;
+                    if (u + 1 < W) { ra += Ma[u + 1]; rb += Mb[u + 1]; rc += has_c ? Mc[u + 1] : 0.0f; }
+                    if (u >= 1) { ra -= Ma[u - 1]; rb -= Mb[u - 1]; rc -= has_c ? Mc[u - 1] : 0.0f; }
+                    M1[u] = (ra + 2.0f * rb) + rc;
+                }
+            }
+            __syncthreads();
+            if (kr >= v_end) {
+                const double A = kr < v_max ? tA[kr] : 0.0, Bc = kr < v_max ? tB[kr] : 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) {
+                    if (live[k]) {
+                        if (kr < v_max) uu[k] = fma(Bc, uu[k], A);
+                        const double x = uu[k] + 0.5;
+                        if (x >= 0.0 && x < (double)W) ee[k] += (double)M1[(int)floor(x)];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int i = t + k * kBlock;
+        if (i < W2) {
+            Eout[i] = ee[k];
+            if (energy_out) energy_out[(int64_t)b * W2 + i] = (float)ee[k];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// S13: strict local minima of the energies, below rho * (deepest energy); greedy suppression
+// of minima within d_nms of a deeper accepted one; lane curves by iterating the track.
+__global__ __launch_bounds__(kBlock) void k_peaks(Dev d, ld_lanes* lanes_out, float* curves_out) {
+    extern __shared__ unsigned char smem[];
+    __shared__ int64_t rv[kWaves];
+    __shared__ int ri[kWaves];
+    __shared__ double dred[kWaves];
+    __shared__ int acc[LD_MAX_LANES];
+    __shared__ int s_nacc;
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int W2 = d.W2, H = d.H, v_max = H - 1;
+    const FrameInfo fi = d.info[b];
+    const double* E = d.energy + (int64_t)b * W2;
+    uint8_t* alive = smem;   // W2
+    const double* tA = d.tab + (int64_t)b * 6 * H + 4 * H;
+    const double* tB = tA + H;
+    double mn = INFINITY;
+    for (int i = t; i < W2; i += kBlock) mn = fmin(mn, E[i]);
+    for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, kWave));
+    if (lane_id() == 0) dred[t / kWave] = mn;
+    __syncthreads();
+    mn = dred[0];
+    for (int w = 1; w < kWaves; ++w) mn = fmin(mn, dred[w]);
+    const bool any = !(fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP)) && mn < 0.0;
+    const double thr = d.P.rho_lpv * mn;
+    for (int i = t; i < W2; i += kBlock) {
+        bool a = any && i >= 1 && i + 1 < W2 && E[i] < E[i - 1] && E[i] < E[i + 1] && E[i] < thr;
+        alive[i] = a ? 1 : 0;
+    }
+    if (t == 0) s_nacc = 0;
+    __syncthreads();
+    const int dn = d.P.d_nms > 0 ? d.P.d_nms : max(8, d.W / 64);
+    for (int it = 0; it < LD_MAX_LANES; ++it) {
+        // argmin over the alive minima by (E, i); E is compared through its order-preserving
+        // 64-bit image so that ties fall to the smaller index
+        int64_t key = INT64_MAX;
+        int idx = 0x7fffffff;
+        for (int i = t; i < W2; i += kBlock)
+            if (alive[i]) {
+                const int64_t bits = __double_as_longlong(E[i]);
+                const int64_t k = bits >= 0 ? bits : (bits ^ 0x7fffffffffffffffLL);
+                if (k < key || (k == key && i < idx)) { key = k; idx = i; }
+            }
+        block_argmin_i64(key, idx, rv, ri);
+        if (idx == 0x7fffffff) break;
+        if (t == 0) acc[s_nacc++] = idx;
+        for (int i = t; i < W2; i += kBlock)
+            if (alive[i] && abs(i - idx) <= dn) alive[i] = 0;
+        __syncthreads();
+    }
+    __syncthreads();
+    const int n = s_nacc;
+    if (t == 0) {
+        for (int i = 1; i < n; ++i) {
+            int x = acc[i], j = i - 1;
+            while (j >= 0 && acc[j] > x) { acc[j + 1] = acc[j]; --j; }
+            acc[j + 1] = x;
+        }
+        ld_lanes L;
+        L.n = n;
+        L.flags = fi.flags;
+        L.v_h = fi.v_h;
+        L.v_end = fi.v_end;
+        for (int l = 0; l < LD_MAX_LANES; ++l) {
+            L.u_start[l] = l < n ? acc[l] - d.half : 0;
+            L.energy[l] = l < n ? (float)E[acc[l]] : 0.0f;
+        }
+        lanes_out[b] = L;
+    }
+    __syncthreads();
+    if (curves_out) {
+        float* cv = curves_out + (int64_t)b * LD_MAX_LANES * H;
+        const float fnan = __int_as_float(0x7fc00000);
+        for (int i = t; i < LD_MAX_LANES * H; i += kBlock) cv[i] = fnan;
+        __syncthreads();
+        if (t < n) {
+            double u = (double)(acc[t] - d.half);
+            for (int v = v_max; v >= fi.v_end; --v) {
+                if (v < v_max) u = fma(tB[v], u, tA[v]);
+                cv[(int64_t)t * H + v] = (float)u;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ==========================================================================================
+// Host side: frame objects and the C ABI.
+struct ld_frame_s {
+    Dev d;
+    int batch;          // allocated frames
+    int active;         // frames processed by the next calls
+    void* mem;          // one device allocation holding all scratch
+    size_t mem_bytes;
+    int device;
+    hipStream_t last;
+    int stage;          // 0 nothing, 1 vdisp done, 2 vp done, 3 energy done
+};
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int elem_size(int fmt) { return fmt == LD_DISP_U8 ? 1 : (fmt == LD_DISP_F32 ? 4 : 2); }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+ld_status launch_ok() { return hipGetLastError() == hipSuccess ? LD_OK : LD_E_HIP; }
+
+size_t vdisp_fit_lds(const Dev& d) {
+    return sizeof(int) * (2 * (size_t)d.H + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32);
+}
+
+size_t vpx_fit_lds(const Dev& d) {
+    return sizeof(int) * ((size_t)d.W2 + 2 * ((size_t)d.W2 + 10) + 4 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
+}
+
+size_t energy_lds(const Dev& d) { return sizeof(float) * 6 * (size_t)d.W; }
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 32 * 1024)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+ld_status check_params(const ld_params& p) {
+    if (p.chi < 0 || p.tau_y_max < 0 || p.tau_y_max > 255 || p.tau_x_max < 0 || p.tau_x_max > 5) return LD_E_INVAL;
+    if (p.lambda_y < 0 || p.lambda_x < 0 || p.lambda_y > 1000 || p.lambda_x > 1000) return LD_E_INVAL;
+    if (p.n_hyp < 1 || p.n_hyp > kMaxHyp || p.max_rounds < 1 || p.max_rounds > kMaxRounds) return LD_E_INVAL;
+    if (p.eps_num < 0 || p.eps_den < 1 || p.edge_t < 0 || p.edge_t > 46340) return LD_E_INVAL;
+    if (p.nu != 1 || p.varsigma != 3) return LD_E_INVAL;    // the kernels are built for the paper's box
+    if (!(p.sigma_g > 0.0) || !(p.tr_x >= 0.0) || !(p.tr_y >= 0.0) || !(p.varpi >= 0.0)) return LD_E_INVAL;
+    if (p.d_nms < 0) return LD_E_INVAL;
+    return LD_OK;
+}
+
+ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t* sid, const int64_t* fidx,
+                    int32_t* vdisp_out, double* beta_out, hipStream_t st) {
+    Dev& d = f->d;
+    dim3 g1((d.H + kHistRows - 1) / kHistRows, f->active);
+    const size_t l1 = sizeof(int) * kHistRows * d.D1;
+    const uint8_t* dp = static_cast<const uint8_t*>(disp);
+    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U8>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_F32>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+    else hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U16Q4>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+    if (launch_ok() != LD_OK) return LD_E_HIP;
+    const size_t l2 = vdisp_fit_lds(d);
+    allow_lds(k_vdisp_fit, l2);
+    hipLaunchKernelGGL(k_vdisp_fit, dim3(f->active), dim3(kBlock), l2, st, d, sid, fidx, beta_out);
+    return launch_ok();
+}
+
+ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, const uint64_t* sid,
+                 const int64_t* fidx, const double* seed_gamma, double* vp_out, hipStream_t st) {
+    Dev& d = f->d;
+    dim3 g3((d.W + kBlock - 1) / kBlock, (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
+    const uint8_t* dp = static_cast<const uint8_t*>(disp);
+    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+    else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+    if (launch_ok() != LD_OK) return LD_E_HIP;
+    const size_t l4 = vpx_fit_lds(d);
+    allow_lds(k_vpx_fit, l4);
+    hipLaunchKernelGGL(k_vpx_fit, dim3(f->active), dim3(kBlock), l4, st, d, sid, fidx, seed_gamma, vp_out);
+    return launch_ok();
+}
+
+template <int NC, int NT>
+void launch_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
+    const size_t l = energy_lds(f->d);
+    allow_lds(k_energy<NC, NT>, l);
+    hipLaunchKernelGGL((k_energy<NC, NT>), dim3(f->active), dim3(kBlock), l, st, f->d, mask, eout);
+}
+
+ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
+    const int nc = (f->d.W + kBlock - 1) / kBlock;
+    if (nc <= 2) launch_energy<2, 4>(f, mask, eout, st);
+    else if (nc <= 4) launch_energy<4, 8>(f, mask, eout, st);
+    else if (nc <= 8) launch_energy<8, 16>(f, mask, eout, st);
+    else launch_energy<16, 32>(f, mask, eout, st);
+    return launch_ok();
+}
+
+ld_status run_peaks(ld_frame f, ld_lanes* lanes, float* curves, hipStream_t st) {
+    hipLaunchKernelGGL(k_peaks, dim3(f->active), dim3(kBlock), (size_t)f->d.W2, st, f->d, lanes, curves);
+    return launch_ok();
+}
+
+ld_status check_images(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt) {
+    const Dev& d = f->d;
+    const int es = elem_size(d.fmt);
+    if (disp == nullptr || dpt < (int64_t)d.W * es || dpt % es != 0 || !aligned(disp, es)) return LD_E_INVAL;
+    if (grey != nullptr && gp < d.W) return LD_E_INVAL;
+    return LD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ld_params_default(ld_params* p) {
+    if (!p) return;
+    p->chi = 25; p->tau_y_max = 6; p->tau_x_max = 5; p->lambda_y = 1; p->lambda_x = 1;
+    p->tr_y = 4.0; p->tr_x = 16.0; p->eps_num = 99; p->eps_den = 100; p->varpi = 3.0;
+    p->edge_t = 100; p->sigma_g = 3.5; p->nu = 1; p->varsigma = 3; p->n_hyp = 64; p->max_rounds = 16;
+    p->rho_lpv = 0.25; p->d_nms = 0; p->weight_squared = 0; p->seed = 0;
+}
+
+const char* ld_status_string(ld_status s) {
+    switch (s) {
+        case LD_OK: return "ok";
+        case LD_E_INVAL: return "invalid argument";
+        case LD_E_NOMEM: return "out of device memory";
+        case LD_E_HIP: return "HIP runtime error";
+        case LD_E_STATE: return "step called out of order";
+    }
+    return "unknown status";
+}
+
+ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
+                          const ld_params* p, ld_frame* out) {
+    if (!out) return LD_E_INVAL;
+    *out = nullptr;
+    if (width < 8 || width > 4096 || height < 8 || height > 4096 || batch < 1 || batch > 65535) return LD_E_INVAL;
+    if (fmt < 0 || fmt > 2 || d_max < 1 || d_max > 1023) return LD_E_INVAL;
+    ld_params P;
+    ld_params_default(&P);
+    if (p) P = *p;
+    if (check_params(P) != LD_OK) return LD_E_INVAL;
+    ld_frame f = new (std::nothrow) ld_frame_s();
+    if (!f) return LD_E_NOMEM;
+    Dev& d = f->d;
+    d.W = width; d.H = height; d.D1 = d_max + 1; d.W2 = 2 * width; d.half = width / 2; d.fmt = fmt;
+    d.d_max = d_max; d.B = batch; d.P = P;
+    const size_t B = (size_t)batch, H = (size_t)height, W = (size_t)width, D1 = (size_t)d.D1, W2 = (size_t)d.W2;
+    size_t off[12], o = 0;
+    size_t sz[12] = {
+        B * D1 * H * 4,                 // myT
+        B * D1 * H,                     // back_y
+        B * 2 * D1 * 4,                 // my_pts
+        B * 2 * sizeof(FitRes),         // fit
+        B * sizeof(FrameInfo),          // info
+        B * 6 * H * 8,                  // tab
+        B * H * 4,                      // rowcnt
+        B * H * W * sizeof(ld_edge),    // edges
+        B * H * W2,                     // back_x
+        B * H * 4,                      // mxpath
+        B * W2 * 8,                     // energy
+        B * 6 * kMaxRounds * 4,         // trace
+    };
+    for (int i = 0; i < 12; ++i) { off[i] = o; o += align_up(sz[i]); }
+    if (hipGetDevice(&f->device) != hipSuccess) { delete f; return LD_E_HIP; }
+    if (hipMalloc(&f->mem, o) != hipSuccess) { (void)hipGetLastError(); delete f; return LD_E_NOMEM; }
+    f->mem_bytes = o;
+    char* base = static_cast<char*>(f->mem);
+    d.myT = reinterpret_cast<int32_t*>(base + off[0]);
+    d.back_y = reinterpret_cast<uint8_t*>(base + off[1]);
+    d.my_pts = reinterpret_cast<int32_t*>(base + off[2]);
+    d.fit = reinterpret_cast<FitRes*>(base + off[3]);
+    d.info = reinterpret_cast<FrameInfo*>(base + off[4]);
+    d.tab = reinterpret_cast<double*>(base + off[5]);
+    d.rowcnt = reinterpret_cast<int32_t*>(base + off[6]);
+    d.edges = reinterpret_cast<ld_edge*>(base + off[7]);
+    d.back_x = reinterpret_cast<int8_t*>(base + off[8]);
+    d.mxpath = reinterpret_cast<int32_t*>(base + off[9]);
+    d.energy = reinterpret_cast<double*>(base + off[10]);
+    d.trace = reinterpret_cast<int32_t*>(base + off[11]);
+    // small state starts zeroed so that introspection of an unprocessed frame is defined
+    if (hipMemset(d.info, 0, sz[4]) != hipSuccess || hipMemset(d.trace, 0xff, sz[11]) != hipSuccess ||
+        hipMemset(d.fit, 0, sz[3]) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(f->mem);
+        delete f;
+        return LD_E_HIP;
+    }
+    f->batch = batch;
+    f->active = batch;
+    f->last = nullptr;
+    f->stage = 0;
+    *out = f;
+    return LD_OK;
+}
+
+ld_status ld_frame_destroy(ld_frame f) {
+    if (!f) return LD_OK;
+    ld_status s = LD_OK;
+    if (hipStreamSynchronize(f->last) != hipSuccess) s = LD_E_HIP;
+    if (hipFree(f->mem) != hipSuccess) s = LD_E_HIP;
+    delete f;
+    return s;
+}
+
+ld_status ld_frame_set_active(ld_frame f, int32_t n) {
+    if (!f || n < 1 || n > f->batch) return LD_E_INVAL;
+    f->active = n;
+    return LD_OK;
+}
+
+ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint64_t* stream_ids,
+                   const int64_t* frame_idx, int32_t* vdisp_out, double* beta_out, void* hip_stream) {
+    if (!f) return LD_E_INVAL;
+    if (check_images(f, nullptr, 0, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
+    if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
+    if ((vdisp_out && !aligned(vdisp_out, 4)) || (beta_out && !aligned(beta_out, 8))) return LD_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, vdisp_out, beta_out, st);
+    f->last = st;
+    if (s == LD_OK) f->stage = 1;
+    return s;
+}
+
+ld_status ld_vp_ransac(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
+                       const uint64_t* stream_ids, const int64_t* frame_idx, const double* seed_gamma,
+                       double* vp_out, void* hip_stream) {
+    if (!f) return LD_E_INVAL;
+    if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
+    if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
+    if ((seed_gamma && !aligned(seed_gamma, 8)) || (vp_out && !aligned(vp_out, 8))) return LD_E_INVAL;
+    if (f->stage < 1) return LD_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ld_status s = run_vp(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, seed_gamma, vp_out, st);
+    f->last = st;
+    if (s == LD_OK) f->stage = 2;
+    return s;
+}
+
+ld_status ld_lane_energy(ld_frame f, const uint8_t* cand_mask, float* energy_out, void* hip_stream) {
+    if (!f) return LD_E_INVAL;
+    if (energy_out && !aligned(energy_out, 4)) return LD_E_INVAL;
+    if (f->stage < 2) return LD_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ld_status s = run_energy(f, cand_mask, energy_out, st);
+    f->last = st;
+    if (s == LD_OK) f->stage = 3;
+    return s;
+}
+
+ld_status ld_peaks(ld_frame f, ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    if (!f || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
+    if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
+    if (f->stage < 3) return LD_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ld_status s = run_peaks(f, lanes_out, curves_out, st);
+    f->last = st;
+    return s;
+}
+
+ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
+                    const uint64_t* stream_ids, const int64_t* frame_idx, ld_lanes* lanes_out, float* curves_out,
+                    void* hip_stream) {
+    if (!f || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
+    if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
+    if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
+    if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    f->last = st;
+    ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_vp(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st);
+    f->stage = s == LD_OK ? 3 : 0;
+    return s;
+}
+
+ld_status ld_sync(ld_frame f) {
+    if (!f) return LD_E_INVAL;
+    return hipStreamSynchronize(f->last) == hipSuccess ? LD_OK : LD_E_HIP;
+}
+
+ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t bytes, void* hip_stream) {
+    if (!f || !dst || b < 0 || b >= f->batch) return LD_E_INVAL;
+    const Dev& d = f->d;
+    const void* src = nullptr;
+    size_t n = 0;
+    switch (what) {
+        case LD_STATE_INFO: src = d.info + b; n = sizeof(FrameInfo); break;
+        case LD_STATE_MY_PATH: src = d.my_pts + (size_t)b * 2 * d.D1; n = sizeof(int32_t) * 2 * d.D1; break;
+        case LD_STATE_BETA: src = d.fit + 2 * (size_t)b; n = sizeof(FitRes); break;
+        case LD_STATE_GAMMA: src = d.fit + 2 * (size_t)b + 1; n = sizeof(FitRes); break;
+        case LD_STATE_TABLES: src = d.tab + (size_t)b * 6 * d.H; n = sizeof(double) * 6 * d.H; break;
+        case LD_STATE_ROWCOUNT: src = d.rowcnt + (size_t)b * d.H; n = sizeof(int32_t) * d.H; break;
+        case LD_STATE_EDGES: src = d.edges + (size_t)b * d.H * d.W; n = sizeof(ld_edge) * d.H * d.W; break;
+        case LD_STATE_MX_PATH: src = d.mxpath + (size_t)b * d.H; n = sizeof(int32_t) * d.H; break;
+        case LD_STATE_ENERGY: src = d.energy + (size_t)b * d.W2; n = sizeof(double) * d.W2; break;
+        case LD_STATE_TRACE: src = d.trace + (size_t)b * 6 * kMaxRounds; n = sizeof(int32_t) * 6 * kMaxRounds; break;
+        default: return LD_E_INVAL;
+    }
+    if (bytes < (int64_t)n) return LD_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    return hipMemcpyAsync(dst, src, n, hipMemcpyDefault, st) == hipSuccess ? LD_OK : LD_E_HIP;
+}
+
+}  // extern "C"

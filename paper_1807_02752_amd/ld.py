@@ -1,0 +1,260 @@
+"""Python binding of libld.so (include/ld.h): argument marshalling only.
+
+Every step of the lane-detection path runs in the library's HIP kernels.  PyTorch only
+provides device memory and streams: tensors are passed by data_ptr() and the current
+torch stream's handle.  If the library has not been built, importing works but every call
+raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libld.so")
+
+LD_OK, LD_E_INVAL, LD_E_NOMEM, LD_E_HIP, LD_E_STATE = 0, -1, -2, -3, -4
+LD_DISP_U8, LD_DISP_F32, LD_DISP_U16Q4 = 0, 1, 2
+LD_FLAG_NOROAD, LD_FLAG_NOVP, LD_FLAG_NOCONS_Y, LD_FLAG_NOCONS_X, LD_FLAG_FALLBACK = 1, 2, 4, 8, 16
+LD_MAX_LANES = 16
+(LD_STATE_INFO, LD_STATE_MY_PATH, LD_STATE_BETA, LD_STATE_GAMMA, LD_STATE_TABLES, LD_STATE_ROWCOUNT,
+ LD_STATE_EDGES, LD_STATE_MX_PATH, LD_STATE_ENERGY, LD_STATE_TRACE) = range(10)
+MAX_ROUNDS_STORED = 64
+
+
+class ld_params(C.Structure):
+    _fields_ = [
+        ("chi", C.c_int32), ("tau_y_max", C.c_int32), ("tau_x_max", C.c_int32),
+        ("lambda_y", C.c_int32), ("lambda_x", C.c_int32),
+        ("tr_y", C.c_double), ("tr_x", C.c_double),
+        ("eps_num", C.c_int32), ("eps_den", C.c_int32),
+        ("varpi", C.c_double), ("edge_t", C.c_int32), ("sigma_g", C.c_double),
+        ("nu", C.c_int32), ("varsigma", C.c_int32),
+        ("n_hyp", C.c_int32), ("max_rounds", C.c_int32),
+        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+class ld_lanes(C.Structure):
+    _fields_ = [("n", C.c_int32), ("flags", C.c_int32), ("v_h", C.c_int32), ("v_end", C.c_int32),
+                ("u_start", C.c_int32 * LD_MAX_LANES), ("energy", C.c_float * LD_MAX_LANES)]
+
+
+class ld_fit(C.Structure):
+    _fields_ = [("ok", C.c_int32), ("flags", C.c_int32), ("center", C.c_int32), ("kshift", C.c_int32),
+                ("rounds", C.c_int32), ("n_survivors", C.c_int32),
+                ("coef", C.c_double * 5), ("raw", C.c_double * 5)]
+
+
+LANES_DTYPE = np.dtype([("n", "<i4"), ("flags", "<i4"), ("v_h", "<i4"), ("v_end", "<i4"),
+                        ("u_start", "<i4", (LD_MAX_LANES,)), ("energy", "<f4", (LD_MAX_LANES,))])
+EDGE_DTYPE = np.dtype([("u", "<i2"), ("gx", "<i2"), ("gy", "<i2"), ("bin", "<i2")])
+FIT_DTYPE = np.dtype([("ok", "<i4"), ("flags", "<i4"), ("center", "<i4"), ("kshift", "<i4"),
+                      ("rounds", "<i4"), ("n_survivors", "<i4"), ("coef", "<f8", (5,)), ("raw", "<f8", (5,))])
+assert LANES_DTYPE.itemsize == C.sizeof(ld_lanes)
+assert FIT_DTYPE.itemsize == C.sizeof(ld_fit)
+
+_lib = None
+
+
+class LdError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libld.so; raise if it is missing (there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LdError(f"libld.so not built ({LIB_PATH}); run paper_1807_02752_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.ld_params_default.argtypes = [C.POINTER(ld_params)]
+        L.ld_params_default.restype = None
+        L.ld_frame_create.argtypes = [i32, i32, i32, i32, i32, C.POINTER(ld_params), C.POINTER(vp)]
+        L.ld_frame_destroy.argtypes = [vp]
+        L.ld_frame_set_active.argtypes = [vp, i32]
+        L.ld_vdisp.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp]
+        L.ld_vp_ransac.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.ld_lane_energy.argtypes = [vp, vp, vp, vp]
+        L.ld_peaks.argtypes = [vp, vp, vp, vp]
+        L.ld_detect.argtypes = [vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.ld_sync.argtypes = [vp]
+        L.ld_status_string.argtypes = [i32]
+        L.ld_status_string.restype = C.c_char_p
+        L.ld_frame_read.argtypes = [vp, i32, i32, vp, i64, vp]
+        for name in ("ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
+                     "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_frame_read"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp",
+            "ld_vp_ransac", "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_status_string",
+            "ld_frame_read"]
+
+
+def check(status: int, what: str = "ld call"):
+    if status != LD_OK:
+        msg = lib().ld_status_string(status).decode()
+        raise LdError(f"{what} failed: {msg} ({status})")
+
+
+def params_default(**overrides) -> ld_params:
+    p = ld_params()
+    lib().ld_params_default(C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+# ---------------------------------------------------------------------------- raw C-ABI names
+def ld_params_default(p: ld_params) -> None:
+    lib().ld_params_default(C.byref(p))
+
+
+def ld_frame_create(width, height, batch, fmt, d_max, params=None):
+    h = C.c_void_p()
+    st = lib().ld_frame_create(width, height, batch, fmt, d_max, C.byref(params) if params is not None else None,
+                               C.byref(h))
+    return st, h
+
+
+def ld_frame_destroy(f):
+    return lib().ld_frame_destroy(f)
+
+
+def ld_frame_set_active(f, n):
+    return lib().ld_frame_set_active(f, n)
+
+
+def ld_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, vdisp_out, beta_out, stream):
+    return lib().ld_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, vdisp_out, beta_out, stream)
+
+
+def ld_vp_ransac(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, seed_gamma, vp_out, stream):
+    return lib().ld_vp_ransac(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, seed_gamma, vp_out,
+                              stream)
+
+
+def ld_lane_energy(f, cand_mask, energy_out, stream):
+    return lib().ld_lane_energy(f, cand_mask, energy_out, stream)
+
+
+def ld_peaks(f, lanes_out, curves_out, stream):
+    return lib().ld_peaks(f, lanes_out, curves_out, stream)
+
+
+def ld_detect(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out, stream):
+    return lib().ld_detect(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out,
+                           stream)
+
+
+def ld_sync(f):
+    return lib().ld_sync(f)
+
+
+def ld_status_string(s):
+    return lib().ld_status_string(s).decode()
+
+
+def ld_frame_read(f, what, b, dst, nbytes, stream):
+    return lib().ld_frame_read(f, what, b, dst, nbytes, stream)
+
+
+# ---------------------------------------------------------------------------- torch front end
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_FMT_OF = {"uint8": LD_DISP_U8, "float32": LD_DISP_F32, "uint16": LD_DISP_U16Q4}
+
+
+class Detector:
+    """A frame object for `batch` frames of one size and disparity format.
+
+    Inputs are torch CUDA tensors shaped [B, H, W] (rows may be padded: the row pitch is
+    taken from the tensor's stride).  All calls are asynchronous on torch's current stream.
+    """
+
+    def __init__(self, width: int, height: int, batch: int, fmt: int, d_max: int, params: ld_params | None = None):
+        self.width, self.height, self.batch, self.fmt, self.d_max = width, height, batch, fmt, d_max
+        self.params = params if params is not None else params_default()
+        st, h = ld_frame_create(width, height, batch, fmt, d_max, self.params)
+        check(st, "ld_frame_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ld_frame_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_active(self, n: int):
+        check(ld_frame_set_active(self.handle, n), "ld_frame_set_active")
+
+    @staticmethod
+    def _pitch(t):
+        return t.stride(-2) * t.element_size()
+
+    def vdisp(self, disp, stream_ids=None, frame_idx=None, vdisp_out=None, beta_out=None):
+        check(ld_vdisp(self.handle, _ptr(disp), self._pitch(disp), _ptr(stream_ids), _ptr(frame_idx),
+                       _ptr(vdisp_out), _ptr(beta_out), _stream()), "ld_vdisp")
+
+    def vp_ransac(self, grey, disp, stream_ids=None, frame_idx=None, seed_gamma=None, vp_out=None):
+        check(ld_vp_ransac(self.handle, _ptr(grey), self._pitch(grey), _ptr(disp), self._pitch(disp),
+                           _ptr(stream_ids), _ptr(frame_idx), _ptr(seed_gamma), _ptr(vp_out), _stream()),
+              "ld_vp_ransac")
+
+    def lane_energy(self, cand_mask=None, energy_out=None):
+        check(ld_lane_energy(self.handle, _ptr(cand_mask), _ptr(energy_out), _stream()), "ld_lane_energy")
+
+    def peaks(self, lanes_out, curves_out=None):
+        check(ld_peaks(self.handle, _ptr(lanes_out), _ptr(curves_out), _stream()), "ld_peaks")
+
+    def detect(self, grey, disp, lanes_out, stream_ids=None, frame_idx=None, curves_out=None):
+        check(ld_detect(self.handle, _ptr(grey), self._pitch(grey), _ptr(disp), self._pitch(disp),
+                        _ptr(stream_ids), _ptr(frame_idx), _ptr(lanes_out), _ptr(curves_out), _stream()),
+              "ld_detect")
+
+    def sync(self):
+        check(ld_sync(self.handle), "ld_sync")
+
+    def lanes_buffer(self, n=None):
+        import torch
+        return torch.empty((n or self.batch) * LANES_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def parse_lanes(buf) -> np.ndarray:
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=LANES_DTYPE)
+
+    def read(self, what: int, b: int = 0) -> np.ndarray:
+        """Copy one piece of frame b's device state to the host (synchronous)."""
+        import torch
+        H, W, D1 = self.height, self.width, self.d_max + 1
+        spec = {
+            LD_STATE_INFO: (np.int32, 8), LD_STATE_MY_PATH: (np.int32, 2 * D1), LD_STATE_BETA: (FIT_DTYPE, 1),
+            LD_STATE_GAMMA: (FIT_DTYPE, 1), LD_STATE_TABLES: (np.float64, 6 * H), LD_STATE_ROWCOUNT: (np.int32, H),
+            LD_STATE_EDGES: (EDGE_DTYPE, H * W), LD_STATE_MX_PATH: (np.int32, H),
+            LD_STATE_ENERGY: (np.float64, 2 * W), LD_STATE_TRACE: (np.int32, 6 * MAX_ROUNDS_STORED),
+        }[what]
+        dt = np.dtype(spec[0])
+        nbytes = dt.itemsize * spec[1]
+        host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        check(ld_frame_read(self.handle, what, b, C.c_void_p(host.data_ptr()), nbytes, _stream()), "ld_frame_read")
+        torch.cuda.current_stream().synchronize()
+        return np.frombuffer(host.numpy().tobytes(), dtype=dt)

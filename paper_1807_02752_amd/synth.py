@@ -3,7 +3,7 @@
 This module only draws scenes and renders them: a left grey image, its disparity map
 and the scene parameters that produced them.  It holds none of the lane detector's
 arithmetic; ground-truth quantities that follow from the scene geometry are derived in
-the tests.  Both the CPU oracle and the GPU path consume exactly these arrays.
+the tests.  The CPU reference and the GPU path consume exactly these arrays.
 
 Scene model (Sec. 2.2 and 2.3 of the paper: a road whose projection on the v-disparity
 map is a parabola, lane markings that share a per-row vanishing point):
