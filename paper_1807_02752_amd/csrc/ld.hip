@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ld_device.h"
 
@@ -975,8 +976,20 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Dev d, ld_lanes* lanes_out, fl
 
 // ==========================================================================================
 // Host side: frame objects and the C ABI.
+constexpr int kNumKernels = 6;   // k_vdisp_hist, k_vdisp_fit, k_edges, k_vpx_fit, k_energy, k_peaks
+
+struct ProfEvent {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
 struct ld_frame_s {
     Dev d;
+    bool prof = false;                  // bracket every kernel launch with HIP events
+    std::vector<ProfEvent> pending;     // recorded, not yet read
+    std::vector<ProfEvent> pool;        // reusable event pairs
+    double acc_ms[kNumKernels] = {0, 0, 0, 0, 0, 0};
+    int64_t calls[kNumKernels] = {0, 0, 0, 0, 0, 0};
     int batch;          // allocated frames
     int active;         // frames processed by the next calls
     void* mem;          // one device allocation holding all scratch
@@ -995,6 +1008,33 @@ int elem_size(int fmt) { return fmt == LD_DISP_U8 ? 1 : (fmt == LD_DISP_F32 ? 4 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 ld_status launch_ok() { return hipGetLastError() == hipSuccess ? LD_OK : LD_E_HIP; }
+
+// Optional per-kernel timing: an event pair on the launch stream around one kernel.
+struct ProfScope {
+    ld_frame f;
+    int kernel;
+    hipStream_t st;
+    ProfEvent ev;
+    bool on;
+    ProfScope(ld_frame f_, int k, hipStream_t s) : f(f_), kernel(k), st(s), on(f_->prof) {
+        if (!on) return;
+        if (f->pool.empty()) {
+            ProfEvent e;
+            e.kernel = 0;
+            if (hipEventCreate(&e.start) != hipSuccess || hipEventCreate(&e.stop) != hipSuccess) { on = false; return; }
+            f->pool.push_back(e);
+        }
+        ev = f->pool.back();
+        f->pool.pop_back();
+        ev.kernel = kernel;
+        (void)hipEventRecord(ev.start, st);
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(ev.stop, st);
+        f->pending.push_back(ev);
+    }
+};
 
 size_t vdisp_fit_lds(const Dev& d) {
     return sizeof(int) * (2 * (size_t)d.H + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32);
@@ -1029,13 +1069,19 @@ ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t*
     dim3 g1((d.H + kHistRows - 1) / kHistRows, f->active);
     const size_t l1 = sizeof(int) * kHistRows * d.D1;
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
-    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U8>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
-    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_F32>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
-    else hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U16Q4>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+    {
+        ProfScope ps(f, 0, st);
+        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U8>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_F32>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+        else hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U16Q4>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+    }
     if (launch_ok() != LD_OK) return LD_E_HIP;
     const size_t l2 = vdisp_fit_lds(d);
     allow_lds(k_vdisp_fit, l2);
-    hipLaunchKernelGGL(k_vdisp_fit, dim3(f->active), dim3(kBlock), l2, st, d, sid, fidx, beta_out);
+    {
+        ProfScope ps(f, 1, st);
+        hipLaunchKernelGGL(k_vdisp_fit, dim3(f->active), dim3(kBlock), l2, st, d, sid, fidx, beta_out);
+    }
     return launch_ok();
 }
 
@@ -1044,13 +1090,19 @@ ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, 
     Dev& d = f->d;
     dim3 g3((d.W + kBlock - 1) / kBlock, (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
-    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
-    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
-    else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+    {
+        ProfScope ps(f, 2, st);
+        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+        else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+    }
     if (launch_ok() != LD_OK) return LD_E_HIP;
     const size_t l4 = vpx_fit_lds(d);
     allow_lds(k_vpx_fit, l4);
-    hipLaunchKernelGGL(k_vpx_fit, dim3(f->active), dim3(kBlock), l4, st, d, sid, fidx, seed_gamma, vp_out);
+    {
+        ProfScope ps(f, 3, st);
+        hipLaunchKernelGGL(k_vpx_fit, dim3(f->active), dim3(kBlock), l4, st, d, sid, fidx, seed_gamma, vp_out);
+    }
     return launch_ok();
 }
 
@@ -1062,6 +1114,7 @@ void launch_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st)
 }
 
 ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
+    ProfScope ps(f, 4, st);
     const int nc = (f->d.W + kBlock - 1) / kBlock;
     if (nc <= 2) launch_energy<2, 4>(f, mask, eout, st);
     else if (nc <= 4) launch_energy<4, 8>(f, mask, eout, st);
@@ -1071,6 +1124,7 @@ ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t s
 }
 
 ld_status run_peaks(ld_frame f, ld_lanes* lanes, float* curves, hipStream_t st) {
+    ProfScope ps(f, 5, st);
     hipLaunchKernelGGL(k_peaks, dim3(f->active), dim3(kBlock), (size_t)f->d.W2, st, f->d, lanes, curves);
     return launch_ok();
 }
@@ -1173,6 +1227,8 @@ ld_status ld_frame_destroy(ld_frame f) {
     if (!f) return LD_OK;
     ld_status s = LD_OK;
     if (hipStreamSynchronize(f->last) != hipSuccess) s = LD_E_HIP;
+    for (auto& e : f->pending) { (void)hipEventDestroy(e.start); (void)hipEventDestroy(e.stop); }
+    for (auto& e : f->pool) { (void)hipEventDestroy(e.start); (void)hipEventDestroy(e.stop); }
     if (hipFree(f->mem) != hipSuccess) s = LD_E_HIP;
     delete f;
     return s;
@@ -1253,6 +1309,37 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
 ld_status ld_sync(ld_frame f) {
     if (!f) return LD_E_INVAL;
     return hipStreamSynchronize(f->last) == hipSuccess ? LD_OK : LD_E_HIP;
+}
+
+ld_status ld_frame_profile(ld_frame f, int32_t enable) {
+    if (!f) return LD_E_INVAL;
+    if (hipStreamSynchronize(f->last) != hipSuccess) return LD_E_HIP;
+    for (auto& e : f->pending) f->pool.push_back(e);
+    f->pending.clear();
+    for (int k = 0; k < kNumKernels; ++k) { f->acc_ms[k] = 0.0; f->calls[k] = 0; }
+    f->prof = enable != 0;
+    return LD_OK;
+}
+
+ld_status ld_frame_kernel_times(ld_frame f, double* ms_out, int64_t* calls_out, int32_t n) {
+    if (!f || !ms_out || n < 1) return LD_E_INVAL;
+    ld_status s = LD_OK;
+    for (auto& e : f->pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(e.stop) != hipSuccess || hipEventElapsedTime(&ms, e.start, e.stop) != hipSuccess) {
+            s = LD_E_HIP;
+        } else {
+            f->acc_ms[e.kernel] += ms;
+            f->calls[e.kernel] += 1;
+        }
+        f->pool.push_back(e);
+    }
+    f->pending.clear();
+    for (int k = 0; k < n && k < kNumKernels; ++k) {
+        ms_out[k] = f->acc_ms[k];
+        if (calls_out) calls_out[k] = f->calls[k];
+    }
+    return s;
 }
 
 ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t bytes, void* hip_stream) {

@@ -86,7 +86,9 @@ def lib():
         L.ld_status_string.argtypes = [i32]
         L.ld_status_string.restype = C.c_char_p
         L.ld_frame_read.argtypes = [vp, i32, i32, vp, i64, vp]
-        for name in ("ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
+        L.ld_frame_profile.argtypes = [vp, i32]
+        L.ld_frame_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+        for name in ("ld_frame_profile", "ld_frame_kernel_times", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
                      "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_frame_read"):
             getattr(L, name).restype = i32
         _lib = L
@@ -95,7 +97,8 @@ def lib():
 
 EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp",
             "ld_vp_ransac", "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_status_string",
-            "ld_frame_read"]
+            "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times"]
+KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks"]
 
 
 def check(status: int, what: str = "ld call"):
@@ -166,6 +169,14 @@ def ld_frame_read(f, what, b, dst, nbytes, stream):
     return lib().ld_frame_read(f, what, b, dst, nbytes, stream)
 
 
+def ld_frame_profile(f, enable):
+    return lib().ld_frame_profile(f, enable)
+
+
+def ld_frame_kernel_times(f, ms_out, calls_out, n):
+    return lib().ld_frame_kernel_times(f, ms_out, calls_out, n)
+
+
 # ---------------------------------------------------------------------------- torch front end
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
@@ -233,6 +244,16 @@ class Detector:
 
     def sync(self):
         check(ld_sync(self.handle), "ld_sync")
+
+    def profile(self, enable: bool = True):
+        check(ld_frame_profile(self.handle, 1 if enable else 0), "ld_frame_profile")
+
+    def kernel_times(self):
+        """{kernel name: (total ms, launches)} since profile(True)."""
+        ms = (C.c_double * len(KERNELS))()
+        calls = (C.c_int64 * len(KERNELS))()
+        check(ld_frame_kernel_times(self.handle, ms, calls, len(KERNELS)), "ld_frame_kernel_times")
+        return {k: (ms[i], calls[i]) for i, k in enumerate(KERNELS)}
 
     def lanes_buffer(self, n=None):
         import torch

@@ -59,30 +59,38 @@ def _rng(seed: int, idx: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(key=key))
 
 
-def _lane_coverage(scene: Scene, k: int, width_fn, dash_k, sub: int = 4):
-    """Area coverage of lane k's marking over every pixel (H x W), anti-aliased.
+def _lane_coverage(scene: Scene, k: int, width_fn, dash_k, cov: np.ndarray, sub: int = 4):
+    """Max-accumulate into `cov` (H x W) the anti-aliased area coverage of lane k's marking.
 
     Each pixel row is split into `sub` sub-rows; on a sub-row the marking is the interval
-    [u_k - hw, u_k + hw] and its overlap with the pixel [u - 0.5, u + 0.5] is exact.
+    [u_k - hw, u_k + hw] and its overlap with the pixel [u - 0.5, u + 0.5] is exact.  Only a
+    window of columns around the marking is evaluated on each row.
     """
     W, H = scene.width, scene.height
-    u = np.arange(W, dtype=np.float64)[None, :]
-    cov = np.zeros((H, W))
     s_k, dashed = scene.lanes[k]
+    vv = np.arange(H, dtype=np.float64)[:, None] + (np.arange(sub)[None, :] + 0.5) / sub - 0.5   # H x sub
+    fv = scene.f(vv)
+    ok = vv >= scene.v0
+    uk = scene.u_c(vv) + s_k * fv
+    hw = 0.5 * width_fn(np.maximum(fv, 0.0))
+    on = ok.astype(np.float64)
+    if dashed and dash_k is not None:
+        phase = np.floor(dash_k / np.maximum(fv, 1e-9))
+        on = on * (np.mod(phase, 2) == 0)
+    lo_u = np.floor(np.min(uk - hw, axis=1)) - 1                # per-row window start
+    span = int(np.ceil(np.max(np.max(uk + hw, axis=1) - lo_u))) + 2
+    span = max(1, min(span, W + 4))
+    cols = lo_u[:, None] + np.arange(span)[None, :]             # H x span
+    c = np.zeros((H, span))
     for j in range(sub):
-        vv = np.arange(H, dtype=np.float64)[:, None] + (j + 0.5) / sub - 0.5
-        fv = scene.f(vv)
-        ok = vv >= scene.v0
-        uk = scene.u_c(vv) + s_k * fv
-        hw = 0.5 * width_fn(np.maximum(fv, 0.0))
-        lo = np.maximum(u - 0.5, uk - hw)
-        hi = np.minimum(u + 0.5, uk + hw)
-        c = np.clip(hi - lo, 0.0, 1.0) * ok
-        if dashed and dash_k is not None:
-            phase = np.floor(dash_k / np.maximum(fv, 1e-9))
-            c = c * (np.mod(phase, 2) == 0)
-        cov += c
-    return cov / sub
+        lo = np.maximum(cols - 0.5, (uk[:, j] - hw[:, j])[:, None])
+        hi = np.minimum(cols + 0.5, (uk[:, j] + hw[:, j])[:, None])
+        c += np.clip(hi - lo, 0.0, 1.0) * on[:, j][:, None]
+    c /= sub
+    inside = (cols >= 0) & (cols < W)
+    rows = np.broadcast_to(np.arange(H)[:, None], cols.shape)
+    r, cc, val = rows[inside], cols[inside].astype(np.int64), c[inside]
+    np.maximum.at(cov, (r, cc), val)
 
 
 def _render(scene: Scene, rng: np.random.Generator, *, disp_noise: float, dropout: float,
@@ -94,7 +102,7 @@ def _render(scene: Scene, rng: np.random.Generator, *, disp_noise: float, dropou
         width_fn = lambda d: np.full_like(d, 3.0)   # noqa: E731  (constant 3 px markings)
     cov = np.zeros((H, W))
     for k in range(len(scene.lanes)):
-        cov = np.maximum(cov, _lane_coverage(scene, k, width_fn, dash_k))
+        _lane_coverage(scene, k, width_fn, dash_k, cov)
     grey = road_value + cov * (lane_value - road_value) + rng.normal(0.0, noise, size=(H, W))
     fv = scene.f(v)                                       # H x 1
     below = (v >= scene.v0)
