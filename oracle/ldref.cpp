@@ -302,7 +302,8 @@ int ldref_sample(int n_cur, int s, uint64_t seed, uint64_t stream_id, int64_t fr
 // counter (frame index, stage<<32 | round, hypothesis, block); each 64-bit word w gives
 // index floor(w * n_cur / 2^64); repeated indices are skipped; at most 16 blocks.
 // A sample with fewer than degree+1 distinct x is invalid.  Hypothesis 0 is replaced by the
-// caller's seed model (raw basis) when one is given.
+// caller's seed model (raw basis) when one is given (a seed whose first coefficient is NaN
+// counts as none).
 // trace (nullable): 3 ints per round: best hypothesis, its inlier count, n_cur.
 int ldref_ransac(const int32_t* x, const int32_t* y, int n0, int degree, double tr,
                  int n_hyp, int max_rounds, int eps_num, int eps_den, uint64_t seed,
@@ -331,7 +332,7 @@ int ldref_ransac(const int32_t* x, const int32_t* y, int n0, int degree, double 
         bool best_is_seed = false;
         for (int h = 0; h < n_hyp; ++h) {
             double model[5] = {0, 0, 0, 0, 0};
-            bool is_seed = (h == 0 && seed_raw != nullptr);
+            bool is_seed = (h == 0 && seed_raw != nullptr && !std::isnan(seed_raw[0]));   // NaN: no seed
             if (is_seed) {
                 for (int p = 0; p <= degree; ++p) model[p] = seed_raw[p];
             } else {

@@ -604,3 +604,12 @@ def test_degenerate_frames_set_flags():
     g, d = synth.degenerate("flat_image")
     r = oracle.detect(g, d, 32)
     assert r.n_edges == 0 and r.n_lanes == 0
+
+
+def test_nan_seed_is_no_seed():
+    """A seed row whose first coefficient is NaN behaves exactly like no seed."""
+    g, d, _ = synth.make_c2(0, 4)
+    a = oracle.detect(g, d, 128)
+    b = oracle.detect(g, d, 128, seed_gamma=np.array([np.nan, 0, 0, 0, 0.0]))
+    assert np.array_equal(a.energy, b.energy) and np.array_equal(a.trace_gamma, b.trace_gamma)
+    assert a.u_start.tolist() == b.u_start.tolist()
