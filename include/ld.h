@@ -36,9 +36,10 @@ extern "C" {
 typedef enum {
     LD_OK = 0,
     LD_E_INVAL = -1,   /* bad argument (null/unaligned pointer, size out of range, ...) */
-    LD_E_NOMEM = -2,   /* device scratch could not be allocated */
+    LD_E_NOMEM = -2,   /* device scratch could not be allocated / not admitted by the budget */
     LD_E_HIP = -3,     /* a HIP runtime call failed (also deferred kernel errors, see ld_sync) */
-    LD_E_STATE = -4    /* a step was called before the step it depends on */
+    LD_E_STATE = -4,   /* a step was called before the step it depends on */
+    LD_E_BUSY = -5     /* the server's queue for this resolution class is full: retry later */
 } ld_status;
 
 /* Disparity pixel formats.  0 marks an invalid (rejected) pixel in every format; an F32
@@ -103,7 +104,8 @@ void ld_params_default(ld_params* p);
 
 /* Create a frame object for `batch` frames of width x height pixels whose disparity is in
  * format `fmt` with bins 0..d_max.  Limits: 8 <= width <= 4096, 8 <= height <= 4096,
- * 1 <= batch <= 65535, 1 <= d_max <= 1023.  p may be NULL (defaults).  The scratch is
+ * 1 <= batch <= 65535, 1 <= d_max <= 1023, width * height * (2 chi + 1) < 2^27 (the row DP
+ * holds its energies in 32 bits; 1920 x 1080 with chi = 25 fits).  p may be NULL (defaults).  The scratch is
  * allocated on the current HIP device (LD_E_NOMEM if it does not fit). */
 ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
                           const ld_params* p, ld_frame* out);
@@ -136,7 +138,8 @@ ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint6
  *  disp, disp_pitch : the same disparity frames as given to ld_vdisp.
  *  stream_ids, frame_idx : as in ld_vdisp (they key the V_px RANSAC samples).
  *  seed_gamma       : nullable device double n x 5, a raw-basis quartic in v used as
- *                     RANSAC hypothesis 0 (a learned or tracked seed).
+ *                     RANSAC hypothesis 0 (a learned or tracked seed); a row whose first
+ *                     coefficient is NaN carries no seed.
  *  vp_out           : nullable device double n x height x 2, (V_px, V_py) per row, NaN
  *                     outside the road rows. */
 ld_status ld_vp_ransac(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
@@ -216,6 +219,72 @@ ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t 
  * nullable) since profiling was enabled. */
 ld_status ld_frame_profile(ld_frame f, int32_t enable);
 ld_status ld_frame_kernel_times(ld_frame f, double* ms_out, int64_t* calls_out, int32_t n);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving: continuous batching of frames from many camera streams.
+ *
+ * The server owns, per resolution class, up to `inflight` batch engines (a frame object of
+ * max_batch frames, device staging for the inputs, its own HIP stream and, if enabled, one
+ * captured HIP graph of the whole path at the full batch whose empty slots are masked).
+ * Engines are created at ld_server_create as long as their device memory fits hbm_budget;
+ * a class that gets no engine does not admit requests (LD_E_NOMEM at submit).
+ * ld_server_submit only queues a request (FIFO per class; LD_E_BUSY when max_queue requests
+ * wait).  ld_server_poll (non-blocking) collects finished batches and starts new ones: a
+ * batch takes queued requests in order, skipping a stream that already has a frame in flight
+ * (each stream's frames run in submission order), up to max_batch, as soon as an engine of
+ * the class is idle, so requests that arrive while others run join the next free engine.
+ * Per-stream state stays in device memory: the last V_px fit (seed of the next frame's
+ * RANSAC hypothesis 0 when seed_from_state is set) and a frame counter; Philox keys are
+ * (seed, stream id) and counters use the stream's frame index, never the batch slot, so a
+ * frame's result does not depend on what it was batched with.
+ */
+typedef struct ld_server_s* ld_server;
+
+#define LD_MAX_CLASSES 4
+
+typedef struct ld_server_config {
+    int32_t n_classes;                      /* 1..LD_MAX_CLASSES */
+    int32_t width[LD_MAX_CLASSES];
+    int32_t height[LD_MAX_CLASSES];
+    int32_t fmt[LD_MAX_CLASSES];            /* ld_disp_format */
+    int32_t d_max[LD_MAX_CLASSES];
+    int32_t max_batch[LD_MAX_CLASSES];      /* frames per engine launch, >= 1 */
+    int32_t n_streams;                      /* stream ids 0..n_streams-1 */
+    int32_t inflight;                       /* engines per class, 1..8 */
+    int32_t max_queue;                      /* waiting requests per class, >= 1 */
+    int32_t use_graphs;                     /* 1: replay a captured graph per engine */
+    int32_t seed_from_state;                /* 1: seed V_px RANSAC with the stream's last fit */
+    int64_t hbm_budget;                     /* bytes of device memory the engines may use */
+} ld_server_config;
+
+/* One finished request.  Times are host seconds (steady clock) at submit and at the poll
+ * that observed completion. */
+typedef struct ld_server_result {
+    int64_t request;
+    int32_t stream_id;
+    int32_t cls;
+    int64_t frame_idx;                      /* the stream's frame counter for this frame */
+    double t_submit;
+    double t_done;
+    ld_lanes lanes;
+} ld_server_result;
+
+/* Create a server on the current HIP device (p may be NULL: defaults). */
+ld_status ld_server_create(const ld_server_config* cfg, const ld_params* p, ld_server* out);
+/* Wait for all in-flight work and free everything.  NULL is accepted. */
+ld_status ld_server_destroy(ld_server s);
+/* Queue one frame of stream stream_id in class cls.  grey/disp are device buffers of one
+ * frame (rows of the given pitches) that the caller keeps alive until the request's result
+ * has been returned by ld_server_poll.  req_out (nullable) receives the request id. */
+ld_status ld_server_submit(ld_server s, int32_t stream_id, int32_t cls, const uint8_t* grey, int64_t grey_pitch,
+                           const void* disp, int64_t disp_pitch, int64_t* req_out);
+/* Collect up to max_results finished requests (host memory) and start batches for queued
+ * requests on idle engines.  Never blocks on the device. */
+ld_status ld_server_poll(ld_server s, ld_server_result* results, int32_t max_results, int32_t* n_out);
+/* Numbers of requests waiting in queues and in flight. */
+ld_status ld_server_pending(ld_server s, int32_t* queued, int32_t* inflight);
+/* Engines created per class and the device bytes they hold. */
+ld_status ld_server_engines(ld_server s, int32_t* per_class /* LD_MAX_CLASSES */, int64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -42,6 +43,7 @@ constexpr int kBig = 0x3FFFFFFF;
 // Device view of a frame object: sizes, parameters and the scratch carried between steps.
 struct Dev {
     int W, H, D1, W2, half, fmt, d_max, B;
+    int hist_rows;      // rows binned by one histogram workgroup
     ld_params P;
     int32_t* myT;       // B x D1 x H   v-disparity counts, transposed (m_y(d, .) contiguous)
     uint8_t* back_y;    // B x D1 x H   v-disparity DP backtrace (tau)
@@ -51,14 +53,21 @@ struct Dev {
     double* tab;        // B x 6 x H    f, f', V_py, V_px, A_v, B_v
     int32_t* rowcnt;    // B x H        road edges per row
     ld_edge* edges;     // B x H x W    per-row edge buckets
-    int8_t* back_x;     // B x H x 2W   row-DP backtrace (tau)
+    int8_t* back_x;     // B x H x ceil(2W/8) x 4 B   row-DP backtrace, 4-bit tie ranks
     int32_t* mxpath;    // B x H        row-DP path columns
     double* energy;     // B x 2W
     int32_t* trace;     // B x 2 x 3 x kMaxRounds
+    float* qbuf;        // B x H x W    G_x w_g of every road edge, in bucket order
+    uint32_t* rbound;   // B x H x 2    raw disparity interval of the road test per row
+    const int32_t* nact;   // nullable device count: frames b >= *nact of a launch are skipped
 };
 
+__device__ __forceinline__ bool frame_masked(const Dev& d, int b) { return d.nact != nullptr && b >= *d.nact; }
+
 // ------------------------------------------------------------------------------------------
-// Block-wide helpers (256 threads)
+// Block-wide helpers (any multiple of 64 threads up to 1024)
+__device__ __forceinline__ int nwaves() { return blockDim.x / kWave; }
+
 __device__ __forceinline__ int block_max_i32(int x, int* red) {
     x = wave_max_i32(x);
     int w = threadIdx.x / kWave;
@@ -66,7 +75,7 @@ __device__ __forceinline__ int block_max_i32(int x, int* red) {
     if (lane_id() == 0) red[w] = x;
     __syncthreads();
     int r = red[0];
-    for (int i = 1; i < kWaves; ++i) r = max(r, red[i]);
+    for (int i = 1; i < nwaves(); ++i) r = max(r, red[i]);
     return r;
 }
 
@@ -77,7 +86,7 @@ __device__ __forceinline__ int block_min_i32(int x, int* red) {
     if (lane_id() == 0) red[w] = x;
     __syncthreads();
     int r = red[0];
-    for (int i = 1; i < kWaves; ++i) r = min(r, red[i]);
+    for (int i = 1; i < nwaves(); ++i) r = min(r, red[i]);
     return r;
 }
 
@@ -88,7 +97,7 @@ __device__ __forceinline__ int block_sum_i32(int x, int* red) {
     if (lane_id() == 0) red[w] = x;
     __syncthreads();
     int r = 0;
-    for (int i = 0; i < kWaves; ++i) r += red[i];
+    for (int i = 0; i < nwaves(); ++i) r += red[i];
     return r;
 }
 
@@ -101,24 +110,24 @@ __device__ __forceinline__ void block_argmin_i64(int64_t& v, int& i, int64_t* rv
     __syncthreads();
     v = rv[0];
     i = ri[0];
-    for (int k = 1; k < kWaves; ++k)
+    for (int k = 1; k < nwaves(); ++k)
         if (rv[k] < v || (rv[k] == v && ri[k] < i)) { v = rv[k]; i = ri[k]; }
 }
 
 // ------------------------------------------------------------------------------------------
 // RANSAC (Alg. "beta/gamma estimation with the assist of RANSAC").  Each round scores up to
 // 64 random samples of DEG+1 points, one per lane of wave 0, and the points are split over
-// the four waves for the inlier count; the best sample's outliers are removed by a stable
+// the waves of the workgroup for the inlier count; the best sample's outliers are removed by a stable
 // ballot compaction; the loop ends when the inliers reach eps of the round's points.  The
 // final model is refitted on the survivors from exact 128-bit moments.
 struct RansacShared {
     double models[kMaxHyp][5];
     int mvalid[kMaxHyp];            // 0 invalid, 1 fitted (s basis), 2 caller seed (raw basis)
-    int counts[kWaves][kMaxHyp];
-    int wsum[kWaves];
-    int red[kWaves];
+    int counts[kMaxWaves][kMaxHyp];
+    int wsum[kMaxWaves];
+    int red[kMaxWaves];
     int best_h, best_n;
-    i128 mred[kWaves][14];
+    i128 mred[kMaxWaves][14];
 };
 
 template <int DEG>
@@ -134,7 +143,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
                              int bitmap_words, RansacShared& S, double tr, const ld_params& P, uint64_t key1,
                              uint64_t ctr0, int stage, const double* seed_raw, FitRes* out, int* trace) {
     constexpr int s = DEG + 1;
-    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave, nw = nwaves(), nt = blockDim.x;
     FitRes res;
     res.ok = 0; res.flags = 0; res.center = 0; res.kshift = 0; res.rounds = 0; res.n_surv = 0;
     for (int p = 0; p < 5; ++p) { res.coef[p] = 0.0; res.raw[p] = 0.0; }
@@ -144,7 +153,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
         return;
     }
     int xmn = 0x7fffffff, xmx = -0x7fffffff;
-    for (int j = t; j < n0; j += kBlock) { xmn = min(xmn, X[j]); xmx = max(xmx, X[j]); }
+    for (int j = t; j < n0; j += nt) { xmn = min(xmn, X[j]); xmx = max(xmx, X[j]); }
     xmn = block_min_i32(xmn, S.red);
     xmx = block_max_i32(xmx, S.red);
     const int center = (xmn + xmx) >> 1;
@@ -153,7 +162,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
     while ((1 << k) < wmax) ++k;
     res.center = center;
     res.kshift = k;
-    for (int j = t; j < n0; j += kBlock) cur[j] = j;
+    for (int j = t; j < n0; j += nt) cur[j] = j;
     const int need = max(s, (n0 + 9) / 10);
     const int n_hyp = min(P.n_hyp, kMaxHyp);
     int n_cur = n0;
@@ -165,7 +174,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
         if (t < n_hyp) {
             double model[5] = {0, 0, 0, 0, 0};
             int kind = 0;
-            if (t == 0 && seed_raw != nullptr) {
+            if (t == 0 && seed_raw != nullptr && !isnan(seed_raw[0])) {   // a NaN seed means none
                 for (int p = 0; p <= DEG; ++p) model[p] = seed_raw[p];
                 kind = 2;
             } else {
@@ -208,7 +217,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
                 cnt = 0;
                 const double* m = S.models[h];
                 const int kind = S.mvalid[h];
-                for (int jj = wave; jj < n_cur; jj += kWaves) {
+                for (int jj = wave; jj < n_cur; jj += nw) {
                     int j = cur[jj];
                     cnt += is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr) ? 1 : 0;
                 }
@@ -221,7 +230,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
             int tot = -1;
             if (lane < n_hyp && S.counts[0][lane] >= 0) {
                 tot = 0;
-                for (int w = 0; w < kWaves; ++w) tot += S.counts[w][lane];
+                for (int w = 0; w < nw; ++w) tot += S.counts[w][lane];
             }
             int bn = tot, bh = lane;
             for (int o = 32; o > 0; o >>= 1) {
@@ -239,7 +248,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
             const double* m = S.models[best_h];
             const int kind = S.mvalid[best_h];
             int base = 0;
-            for (int c0 = 0; c0 < n_cur; c0 += kBlock) {
+            for (int c0 = 0; c0 < n_cur; c0 += nt) {
                 int jj = c0 + t, j = 0;
                 bool pred = false;
                 if (jj < n_cur) {
@@ -251,7 +260,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
                 if (lane == 0) S.wsum[wave] = __popcll(bal);
                 __syncthreads();
                 int off = base, tot = 0;
-                for (int w = 0; w < kWaves; ++w) {
+                for (int w = 0; w < nw; ++w) {
                     if (w < wave) off += S.wsum[w];
                     tot += S.wsum[w];
                 }
@@ -270,19 +279,19 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
     res.flags = converged ? 0 : 1;
     res.n_surv = n_cur;
     // ---- final fit on the survivors: distinct abscissae, exact moments, solve
-    for (int i = t; i < bitmap_words; i += kBlock) bitmap[i] = 0u;
+    for (int i = t; i < bitmap_words; i += nt) bitmap[i] = 0u;
     __syncthreads();
-    for (int jj = t; jj < n_cur; jj += kBlock) {
+    for (int jj = t; jj < n_cur; jj += nt) {
         int x = X[cur[jj]];
         atomicOr(&bitmap[x >> 5], 1u << (x & 31));
     }
     __syncthreads();
     int pc = 0;
-    for (int i = t; i < bitmap_words; i += kBlock) pc += __popc(bitmap[i]);
+    for (int i = t; i < bitmap_words; i += nt) pc += __popc(bitmap[i]);
     const int distinct = block_sum_i32(pc, S.red);
     Moments M;
     moments_zero(M);
-    for (int jj = t; jj < n_cur; jj += kBlock) moments_add<DEG>(M, X[cur[jj]], Y[cur[jj]], center);
+    for (int jj = t; jj < n_cur; jj += nt) moments_add<DEG>(M, X[cur[jj]], Y[cur[jj]], center);
     for (int p = 0; p <= 2 * DEG; ++p) M.sw[p] = wave_sum_i128(M.sw[p]);
     for (int p = 0; p <= DEG; ++p) M.syw[p] = wave_sum_i128(M.syw[p]);
     if (lane == 0) {
@@ -294,7 +303,7 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
         if (distinct >= s) {
             Moments T;
             moments_zero(T);
-            for (int w = 0; w < kWaves; ++w) {
+            for (int w = 0; w < nw; ++w) {
                 for (int p = 0; p <= 2 * DEG; ++p) T.sw[p] += S.mred[w][p];
                 for (int p = 0; p <= DEG; ++p) T.syw[p] += S.mred[w][9 + p];
             }
@@ -309,10 +318,13 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
 }
 
 // ------------------------------------------------------------------------------------------
-// S1: v-disparity histogram m_y(d, v) (Sec. 2.2).  A workgroup bins kHistRows rows of one
-// frame into LDS; within a wave, lanes with the same bin are merged by ballot before one LDS
-// atomic (a road row puts most pixels into one or two bins).
-constexpr int kHistRows = 4;
+// S1: v-disparity histogram m_y(d, v) (Sec. 2.2).  A workgroup bins hist_rows rows of one
+// frame into LDS; within a wave, the lanes that share the first active lane's bin are merged
+// by ballot into one LDS atomic and the other lanes add directly (a road row puts most
+// pixels into one or two bins, so one merge removes most of the same-address traffic).  Rows
+// are loaded four at a time (every load of the four rows in flight), and the counts leave
+// transposed, hist_rows consecutive rows per disparity.
+constexpr int kHistGroup = 4;
 
 template <int FMT>
 __device__ __forceinline__ bool disp_bin(const uint8_t* row, int u, int d_max, int& bin) {
@@ -333,35 +345,48 @@ __device__ __forceinline__ bool disp_bin(const uint8_t* row, int u, int d_max, i
     }
 }
 
-template <int FMT>
+template <int FMT, int NPT>
 __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* disp, int64_t pitch, int32_t* vdisp_out) {
-    extern __shared__ int hist[];   // kHistRows x D1
-    const int b = blockIdx.y, v0 = blockIdx.x * kHistRows, t = threadIdx.x, lane = lane_id();
+    extern __shared__ int hist[];   // hist_rows x D1
+    const int hr = d.hist_rows;
+    const int b = blockIdx.y, v0 = blockIdx.x * hr, t = threadIdx.x, lane = lane_id();
+    if (frame_masked(d, b)) return;
     const int D1 = d.D1, W = d.W, H = d.H;
-    for (int i = t; i < kHistRows * D1; i += kBlock) hist[i] = 0;
+    const int rows = min(hr, H - v0);
+    for (int i = t; i < hr * D1; i += kBlock) hist[i] = 0;
     __syncthreads();
-    for (int r = 0; r < kHistRows; ++r) {
-        const int v = v0 + r;
-        if (v >= H) break;
-        const uint8_t* row = disp + ((int64_t)b * H + v) * pitch;
-        for (int u0 = 0; u0 < W; u0 += kBlock) {
-            const int u = u0 + t;
-            int bin = 0;
-            bool valid = (u < W) && disp_bin<FMT>(row, u, d.d_max, bin);
-            uint64_t act = __ballot(valid);
-            while (act) {
-                const int leader = __ffsll((unsigned long long)act) - 1;
-                const int b0 = __shfl(bin, leader, kWave);
-                const bool same = valid && bin == b0;
-                const uint64_t m = __ballot(same);
-                if (lane == leader) atomicAdd(&hist[r * D1 + b0], __popcll(m));
-                if (same) valid = false;
-                act &= ~m;
+    for (int g = 0; g < rows; g += kHistGroup) {
+        int bins[kHistGroup][NPT];
+        bool ok[kHistGroup][NPT];
+#pragma unroll
+        for (int r = 0; r < kHistGroup; ++r) {
+            const uint8_t* row = disp + ((int64_t)b * H + v0 + g + r) * pitch;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int u = t + k * kBlock;
+                bins[r][k] = 0;
+                ok[r][k] = (g + r < rows) && (u < W) && disp_bin<FMT>(row, u, d.d_max, bins[r][k]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kHistGroup; ++r) {
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const bool valid = ok[r][k];
+                const int bin = bins[r][k];
+                const uint64_t act = __ballot(valid);
+                if (act) {
+                    const int leader = __ffsll((unsigned long long)act) - 1;
+                    const int b0 = __shfl(bin, leader, kWave);
+                    const bool same = valid && bin == b0;
+                    const uint64_t m = __ballot(same);
+                    if (lane == leader) atomicAdd(&hist[(g + r) * D1 + b0], __popcll(m));
+                    if (valid && !same) atomicAdd(&hist[(g + r) * D1 + bin], 1);
+                }
             }
         }
     }
     __syncthreads();
-    const int rows = min(kHistRows, H - v0);
     for (int i = t; i < rows * D1; i += kBlock) {
         const int dd = i / rows, r = i % rows;
         d.myT[((int64_t)b * D1 + dd) * H + v0 + r] = hist[r * D1 + dd];
@@ -378,14 +403,60 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* dis
 // S2 + S3: DP on the v-disparity map (Eq. vpy_estimation), RANSAC road profile beta
 // (Alg. "beta estimation"), tables f, f', V_py (Eq. vpy_equation) and the road rows.  One
 // workgroup per frame; E lives in two LDS rows, the backtrace in global memory.
-__global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
-                                                      double* beta_out) {
+// The road test of Sec. 2.3.1, valid(raw) and |D(raw) - f| <= varpi in FP64, as an interval
+// of raw pixel values.  D is non-decreasing in the raw value over the valid values (u8:
+// 1..255, u16: 1..65535, f32: the bit patterns of positive finite floats) and the rounded
+// difference D - f is non-decreasing in D, so the passing raw values form one interval
+// [lo, hi]; both ends are found by bisection on the same FP64 predicate.  Every invalid raw
+// value (0, negative, infinite or NaN floats) lies outside it.  lo > hi when it is empty.
+__device__ __forceinline__ double raw_to_d(int fmt, uint32_t r) {
+    if (fmt == LD_DISP_U8) return (double)r;
+    if (fmt == LD_DISP_U16Q4) return (double)r / 16.0;
+    return (double)__uint_as_float(r);
+}
+
+__device__ void road_interval(int fmt, double f, double varpi, uint32_t& lo, uint32_t& hi) {
+    const uint32_t top = fmt == LD_DISP_U8 ? 255u : (fmt == LD_DISP_U16Q4 ? 65535u : 0x7F7FFFFFu);
+    lo = 1u;
+    hi = 0u;
+    // smallest r with D(r) - f >= -varpi
+    if (!(raw_to_d(fmt, top) - f >= -varpi)) return;
+    uint32_t a = 1u, z = top;
+    if (!(raw_to_d(fmt, a) - f >= -varpi)) {
+        while (z - a > 1u) {            // predicate false at a, true at z
+            const uint32_t m = a + (z - a) / 2u;
+            if (raw_to_d(fmt, m) - f >= -varpi) z = m; else a = m;
+        }
+        a = z;
+    }
+    // largest r with D(r) - f <= varpi
+    if (!(raw_to_d(fmt, 1u) - f <= varpi)) return;
+    uint32_t x = 1u, y = top;
+    if (!(raw_to_d(fmt, y) - f <= varpi)) {
+        while (y - x > 1u) {            // predicate true at x, false at y
+            const uint32_t m = x + (y - x) / 2u;
+            if (raw_to_d(fmt, m) - f <= varpi) x = m; else y = m;
+        }
+    } else {
+        x = y;
+    }
+    lo = a;
+    hi = x;
+}
+
+constexpr int kVdRows = 4;                 // rows per thread in the v-disparity DP
+constexpr int kVdWalk = 32;                // DP steps of the backtrace staged in LDS per walk chunk
+constexpr int kVdWalkCols = 257;           // staged rows per step (covers kVdWalk steps of tau_max)
+
+__global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                    double* beta_out) {
     extern __shared__ unsigned char smem[];
     __shared__ RansacShared S;
-    __shared__ int64_t rv[kWaves];
-    __shared__ int ri[kWaves];
-    __shared__ int s_n;
-    const int b = blockIdx.x, t = threadIdx.x;
+    __shared__ int64_t rv[kMaxWaves];
+    __shared__ int ri[kMaxWaves];
+    __shared__ int s_n, s_v;
+    const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    if (frame_masked(d, b)) return;
     const int H = d.H, D1 = d.D1, d_max = d.d_max;
     int* E0 = reinterpret_cast<int*>(smem);
     int* E1 = E0 + H;
@@ -395,46 +466,110 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* str
     int* cur2 = cur + D1;
     uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + D1);
     const int bm_words = (H + 31) / 32;
-    const int32_t* myT = d.myT + (int64_t)b * D1 * H;
+    uint8_t* win = reinterpret_cast<uint8_t*>(bitmap + bm_words);   // kVdWalk x kVdWalkCols
     uint8_t* back = d.back_y + (int64_t)b * D1 * H;
+    const int32_t* myT = d.myT + (int64_t)b * D1 * H;
     const int tau_max = d.P.tau_y_max, lam = d.P.lambda_y;
 
-    for (int v = t; v < H; v += kBlock) {
+    for (int v = t; v < H; v += nt) {
         E0[v] = -myT[(int64_t)d_max * H + v];
         d.rowcnt[(int64_t)b * H + v] = 0;
+    }
+    // the column m_y(d, .) of the next DP step is loaded while the current one is computed
+    int nxt[kVdRows];
+#pragma unroll
+    for (int k = 0; k < kVdRows; ++k) {
+        const int v = t + k * nt;
+        nxt[k] = (d_max >= 1 && v < H) ? myT[(int64_t)(d_max - 1) * H + v] : 0;
     }
     __syncthreads();
     int* Ec = E0;
     int* En = E1;
     for (int dd = d_max - 1; dd >= 0; --dd) {
-        for (int v = t; v < H; v += kBlock) {
-            int best = Ec[v], bt = 0;
-            for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
-                int c = Ec[v + tau] + lam * tau;
-                if (c < best) { best = c; bt = tau; }
+        int curm[kVdRows];
+#pragma unroll
+        for (int k = 0; k < kVdRows; ++k) curm[k] = nxt[k];
+        if (dd >= 1) {
+#pragma unroll
+            for (int k = 0; k < kVdRows; ++k) {
+                const int v = t + k * nt;
+                nxt[k] = v < H ? myT[(int64_t)(dd - 1) * H + v] : 0;
             }
-            En[v] = -myT[(int64_t)dd * H + v] + best;
-            back[(int64_t)dd * H + v] = (uint8_t)bt;
+        }
+#pragma unroll
+        for (int k = 0; k < kVdRows; ++k) {
+            const int v = t + k * nt;
+            if (v < H) {
+                int best = Ec[v], bt = 0;
+                for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
+                    const int c = Ec[v + tau] + lam * tau;
+                    if (c < best) { best = c; bt = tau; }
+                }
+                En[v] = -curm[k] + best;
+                back[(int64_t)dd * H + v] = (uint8_t)bt;
+            }
         }
         __syncthreads();
         int* tmp = Ec; Ec = En; En = tmp;
     }
     int64_t bv = INT64_MAX;
     int bi = 0x7fffffff;
-    for (int v = t; v < H; v += kBlock)
+    for (int v = t; v < H; v += nt)
         if ((int64_t)Ec[v] < bv) { bv = Ec[v]; bi = v; }
     block_argmin_i64(bv, bi, rv, ri);
-    if (t == 0) {
-        int v = bi, n = 0;
-        for (int dd = 0; dd <= d_max; ++dd) {
-            if (myT[(int64_t)dd * H + v] > 0) { PX[n] = v; PY[n] = dd; ++n; }
-            if (dd < d_max) v += back[(int64_t)dd * H + v];
-        }
-        s_n = n;
-    }
+    // backtrace: stage the rows the path can reach in the next kVdWalk steps, then one thread
+    // follows it (the path moves down by at most tau_max rows per step)
+    const int steps = max(1, min(kVdWalk, (kVdWalkCols - 1) / max(1, tau_max)));
+    if (t == 0) s_v = bi;
     __syncthreads();
+    for (int d0 = 0; d0 <= d_max; d0 += steps) {
+        const int v0 = s_v;
+        const int nst = min(steps, d_max - d0);               // steps with a backtrace entry
+        const int ncols = min(H - v0, tau_max * steps + 1);
+        for (int i = t; i < nst * ncols; i += nt) {
+            const int r = i / ncols, c = i % ncols;
+            win[r * kVdWalkCols + c] = back[(int64_t)(d0 + r) * H + v0 + c];
+        }
+        __syncthreads();
+        if (t == 0) {
+            int v = v0;
+            const int last = min(d0 + steps - 1, d_max);
+            for (int dd = d0; dd <= last; ++dd) {
+                cur[dd] = v;                                    // row of disparity dd on the path
+                if (dd < d_max) v += win[(dd - d0) * kVdWalkCols + (v - v0)];
+            }
+            s_v = v;
+        }
+        __syncthreads();
+    }
+    // keep the path points that carry votes, in order of disparity (stable ballot compaction)
+    {
+        const int lane = lane_id(), wave = t / kWave, nw = nwaves();
+        int base = 0;
+        for (int c0 = 0; c0 <= d_max; c0 += nt) {
+            const int dd = c0 + t;
+            const bool pred = dd <= d_max && myT[(int64_t)dd * H + cur[dd]] > 0;
+            const uint64_t bal = __ballot(pred);
+            if (lane == 0) S.wsum[wave] = __popcll(bal);
+            __syncthreads();
+            int off = base, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                if (w < wave) off += S.wsum[w];
+                tot += S.wsum[w];
+            }
+            if (pred) {
+                const int o = off + __popcll(bal & lanes_below());
+                PX[o] = cur[dd];
+                PY[o] = dd;
+            }
+            base += tot;
+            __syncthreads();
+        }
+        if (t == 0) s_n = base;
+        __syncthreads();
+    }
     const int n_my = s_n;
-    for (int i = t; i < n_my; i += kBlock) {
+    for (int i = t; i < n_my; i += nt) {
         d.my_pts[(int64_t)b * 2 * D1 + i] = PX[i];
         d.my_pts[(int64_t)b * 2 * D1 + D1 + i] = PY[i];
     }
@@ -454,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* str
     int bad = -1;
     if (ok) {
         const double sc = ldexp(1.0, -beta.kshift);
-        for (int v = t; v < H; v += kBlock) {
+        for (int v = t; v < H; v += nt) {
             double s = (double)(v - beta.center) * sc;
             double fv = beta.coef[2];
             fv = fv * s + beta.coef[1];
@@ -466,9 +601,13 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* str
             tvpy[v] = (double)v - fv / dv;
             tvpx[v] = nan;
             if (!(fv > 0.0 && dv > 0.0)) bad = max(bad, v);
+            uint32_t lo, hi;
+            road_interval(d.fmt, fv, d.P.varpi, lo, hi);
+            d.rbound[((int64_t)b * H + v) * 2] = lo;
+            d.rbound[((int64_t)b * H + v) * 2 + 1] = hi;
         }
     } else {
-        for (int v = t; v < H; v += kBlock) { tf[v] = nan; tfp[v] = nan; tvpy[v] = nan; tvpx[v] = nan; }
+        for (int v = t; v < H; v += nt) { tf[v] = nan; tfp[v] = nan; tvpy[v] = nan; tvpx[v] = nan; }
     }
     bad = block_max_i32(bad, S.red);
     if (t == 0) {
@@ -492,78 +631,103 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_fit(Dev d, const uint64_t* str
 // ------------------------------------------------------------------------------------------
 // S4 + S5: Sobel gradient on the road rows, road mask (Sec. 2.3.1), edge test, and the V_px
 // vote of every road edge (Eq. sparse_vpx_estimation with the gradient read as the edge
-// slope).  A workgroup covers kBlock columns x kEdgeRows rows; edges are appended to their
-// row's bucket with one atomic per wave.
-constexpr int kEdgeRows = 8;
-
+// slope).  One wave covers 256 columns x kEdgeRows rows of one frame, four consecutive
+// columns per lane: each lane slides a 3-row window of six grey bytes (columns ub-1 .. ub+4)
+// down its columns, loading one new row per step, with the next row's raw disparities in
+// flight.  The road test is an integer compare against the row's raw interval.  A row's
+// edges are appended to its bucket with one atomic per wave.
+constexpr int kEdgeRows = 16;
+constexpr int kQT = 64;                 // threads per workgroup (one wave), 4 columns each
 template <int FMT>
-__device__ __forceinline__ bool disp_value(const uint8_t* row, int u, double& D) {
-    if (FMT == LD_DISP_U8) {
-        int r = row[u];
-        D = (double)r;
-        return r != 0;
-    } else if (FMT == LD_DISP_F32) {
-        float x = reinterpret_cast<const float*>(row)[u];
-        D = (double)x;
-        return isfinite(x) && x > 0.0f;
-    } else {
-        int r = reinterpret_cast<const uint16_t*>(row)[u];
-        D = (double)r / 16.0;
-        return r != 0;
-    }
+__device__ __forceinline__ uint32_t disp_raw(const uint8_t* row, int u) {
+    if (FMT == LD_DISP_U8) return row[u];
+    if (FMT == LD_DISP_F32) return reinterpret_cast<const uint32_t*>(row)[u];
+    return reinterpret_cast<const uint16_t*>(row)[u];
 }
-
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
-                                                  int64_t dpitch) {
-    const int b = blockIdx.z, v0 = blockIdx.y * kEdgeRows, u = blockIdx.x * kBlock + threadIdx.x;
-    const int W = d.W, H = d.H, lane = lane_id();
+__global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
+                                               int64_t dpitch) {
+    const int b = blockIdx.z, vb = blockIdx.y * kEdgeRows, lane = threadIdx.x;
+    if (frame_masked(d, b)) return;
+    const int ub = (blockIdx.x * kQT + lane) * 4;
+    const int W = d.W, H = d.H;
     const FrameInfo fi = d.info[b];
     if (fi.flags & LD_FLAG_NOROAD) return;
-    if (v0 + kEdgeRows <= fi.v_h) return;
-    const double* tf = d.tab + (int64_t)b * 6 * H;
-    const double* tvpy = tf + 2 * H;
-    const int64_t t2 = (int64_t)d.P.edge_t * d.P.edge_t;
-    const double varpi = d.P.varpi;
-    for (int r = 0; r < kEdgeRows; ++r) {
-        const int v = v0 + r;
-        if (v < fi.v_h || v >= H) continue;
-        bool edge = false;
-        int gx = 0, gy = 0, bin = -1;
-        if (u < W) {
-            double D;
-            const uint8_t* drow = disp + ((int64_t)b * H + v) * dpitch;
-            if (disp_value<FMT>(drow, u, D) && fabs(D - tf[v]) <= varpi && u >= 1 && u <= W - 2 && v >= 1 &&
-                v <= H - 2) {
-                const uint8_t* g0 = grey + ((int64_t)b * H + v - 1) * gpitch;
-                const uint8_t* g1 = g0 + gpitch;
-                const uint8_t* g2 = g1 + gpitch;
-                const int a0 = g0[u - 1], a1 = g0[u], a2 = g0[u + 1];
-                const int b0 = g1[u - 1], b2 = g1[u + 1];
-                const int c0 = g2[u - 1], c1 = g2[u], c2 = g2[u + 1];
-                gx = (a2 - a0) + 2 * (b2 - b0) + (c2 - c0);
-                gy = (c0 - a0) + 2 * (c1 - a1) + (c2 - a2);
-                edge = (int64_t)gx * gx + (int64_t)gy * gy > t2;
+    const int vs = max(vb, fi.v_h), ve = min(vb + kEdgeRows - 1, H - 1);
+    if (vs > ve) return;
+    const double* tvpy = d.tab + (int64_t)b * 6 * H + 2 * H;
+    const uint32_t* rb = d.rbound + (int64_t)b * H * 2;
+    const int t2 = d.P.edge_t * d.P.edge_t;
+    auto load_row = [&](int v, int* x) {     // x[0] = column ub-1 .. x[5] = ub+4, zero outside
+        const bool rok = v >= 0 && v < H;
+        const uint8_t* g = grey + ((int64_t)b * H + (rok ? v : 0)) * gpitch;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int u = ub - 1 + k;
+            x[k] = (rok && u >= 0 && u < W) ? (int)g[u] : 0;
+        }
+    };
+    int xa[6], xm[6], xc[6];
+    load_row(vs - 1, xa);
+    load_row(vs, xm);
+    uint32_t rc[4], rn[4];
+    auto load_raw = [&](int v, uint32_t* r) {
+        const uint8_t* dr = disp + ((int64_t)b * H + (v <= ve ? v : vs)) * dpitch;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = (v <= ve && ub + k < W) ? disp_raw<FMT>(dr, ub + k) : 0u;
+    };
+    load_raw(vs, rc);
+    for (int v = vs; v <= ve; ++v) {
+        load_row(v + 1, xc);
+        load_raw(v + 1, rn);
+        const bool vin = v >= 1 && v <= H - 2;
+        const uint32_t lo = rb[2 * v], hi = rb[2 * v + 1];
+        uint32_t rec[4];
+        int binv[4];
+        uint64_t bal[4];
+        uint32_t emask = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int u = ub + k;
+            int gx = 0, gy = 0, bin = -1;
+            bool edge = false;
+            if (vin && u >= 1 && u <= W - 2 && rc[k] >= lo && rc[k] <= hi) {
+                gx = (xa[k + 2] - xa[k]) + 2 * (xm[k + 2] - xm[k]) + (xc[k + 2] - xc[k]);
+                gy = (xc[k] - xa[k]) + 2 * (xc[k + 1] - xa[k + 1]) + (xc[k + 2] - xa[k + 2]);
+                edge = gx * gx + gy * gy > t2;
                 if (edge && gx != 0) {
-                    double tt = (double)v - tvpy[v];
-                    double x = (double)u + (tt * (double)gy) / (double)gx;
-                    double bf = floor(x + 0.5);
+                    const double tt = (double)v - tvpy[v];
+                    const double x = (double)u + (tt * (double)gy) / (double)gx;
+                    const double bf = floor(x + 0.5);
                     if (bf >= -(double)d.half && bf < (double)(d.W2 - d.half)) bin = (int)bf + d.half;
                 }
             }
+            rec[k] = ((uint32_t)gx & 0xffffu) | ((uint32_t)gy << 16);
+            binv[k] = bin;
+            emask |= edge ? (1u << k) : 0u;
+            bal[k] = __ballot(edge);
         }
-        const uint64_t bal = __ballot(edge);
-        if (bal) {
-            const int leader = __ffsll((unsigned long long)bal) - 1;
+        const int tot = __popcll(bal[0]) + __popcll(bal[1]) + __popcll(bal[2]) + __popcll(bal[3]);
+        if (tot > 0) {
             int base = 0;
-            if (lane == leader) base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], __popcll(bal));
-            base = __shfl(base, leader, kWave);
-            if (edge) {
-                ld_edge e;
-                e.u = (int16_t)u; e.gx = (int16_t)gx; e.gy = (int16_t)gy; e.bin = (int16_t)bin;
-                d.edges[((int64_t)b * H + v) * W + base + __popcll(bal & lanes_below())] = e;
+            if (lane == 0) base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], tot);
+            int off = __shfl(base, 0, kWave);
+            ld_edge* out = d.edges + ((int64_t)b * H + v) * W;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (emask & (1u << k)) {
+                    ld_edge e;
+                    e.u = (int16_t)(ub + k); e.gx = (int16_t)(rec[k] & 0xffffu); e.gy = (int16_t)(rec[k] >> 16);
+                    e.bin = (int16_t)binv[k];
+                    out[off + __popcll(bal[k] & lanes_below())] = e;
+                }
+                off += __popcll(bal[k]);
             }
         }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { xa[k] = xm[k]; xm[k] = xc[k]; }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rc[k] = rn[k];
     }
 }
 
@@ -571,25 +735,63 @@ __global__ __launch_bounds__(kBlock) void k_edges(Dev d, const uint8_t* grey, in
 // S6 + S7 + S8: band accumulator m_x (Alg. "Dense V_px accumulation", a band of 2 chi + 1 rows
 // clipped to the road), DP path over the 2W vote columns (Eq. dense_vpx_estimation), RANSAC
 // quartic gamma (Alg. "gamma estimation"), V_px table (Eq. vpx_estimation) and the
-// coefficients of the lane track of Eq. lane_visualisation.  One workgroup per frame: the
-// band histogram and two padded DP rows live in LDS, the backtrace in global memory.
-__device__ __forceinline__ void band_row(const Dev& d, int b, int v, int sign, int* hist) {
-    const int cnt = d.rowcnt[(int64_t)b * d.H + v];
-    const ld_edge* e = d.edges + ((int64_t)b * d.H + v) * d.W;
-    for (int i = threadIdx.x; i < cnt; i += kBlock) {
-        const int bin = e[i].bin;
-        if (bin >= 0) atomicAdd(&hist[bin], sign);
+// coefficients of the lane track of Eq. lane_visualisation.  One workgroup per frame, one
+// thread per run of kDpRun consecutive columns.
+//
+// DP step.  The value E + lambda|tau| and the tie rank of tau in the scan order
+// 0, -1, +1, -2, +2, ... (0..10) are packed into one key (value << 4 | rank): the minimum key
+// is the minimum value with the first tau of the scan order, which is exactly the
+// first-strict-minimum rule.  With Sh = E << 4 the key of tau = -a is
+// Sh(c') - (16 lambda + 2) c' + ((16 lambda + 2) c - 1) and of tau = +a is
+// Sh(c') + (16 lambda + 2) c' - (16 lambda + 2) c (c' = c + tau), so each side is a plain
+// minimum of a per-column term over a window, plus a per-c constant.  The rank (4 bits) is
+// the backtrace, eight columns per 32-bit word.
+constexpr int kDpRun = 8;
+constexpr int kWalkRows = 32;        // rows of the backtrace staged in LDS per walk chunk
+
+// The band edges of one row, up to kBandPer per thread (a row holds at most W edges and the
+// workgroup has at least W/4 threads).
+constexpr int kBandPer = 4;
+
+__device__ __forceinline__ void band_load(const ld_edge* row_edges, int cnt, int* bins) {
+#pragma unroll
+    for (int k = 0; k < kBandPer; ++k) {
+        const int i = threadIdx.x + k * blockDim.x;
+        bins[k] = i < cnt ? row_edges[i].bin : -1;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
-                                                    const double* seed_gamma, double* vp_out) {
+__device__ __forceinline__ int* smem_i(unsigned char* p) { return reinterpret_cast<int*>(p); }
+
+// position of column c (c >= -8) in a run-interleaved row with NR runs
+__device__ __forceinline__ int ipos(int c, int NR) { return (c & (kDpRun - 1)) * NR + (c >> 3) + 1; }
+
+__device__ __forceinline__ void band_apply(const int* bins, int sign, int* hist, int NR) {
+#pragma unroll
+    for (int k = 0; k < kBandPer; ++k)
+        if (bins[k] >= 0) atomicAdd(&hist[ipos(bins[k], NR)], sign);
+}
+
+__host__ __device__ __forceinline__ int vpx_walk_words_dev(int W2) {
+    const int nwords = (W2 + kDpRun - 1) / kDpRun;
+    const int ww = 2 * (5 * kWalkRows) / kDpRun + 2;
+    return kWalkRows * (nwords < ww ? nwords : ww);
+}
+
+__device__ __forceinline__ int rank_to_tau(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                  const double* seed_gamma, double* vp_out) {
     extern __shared__ unsigned char smem[];
     __shared__ RansacShared S;
-    __shared__ int64_t rv[kWaves];
-    __shared__ int ri[kWaves];
-    const int b = blockIdx.x, t = threadIdx.x;
+    __shared__ int64_t rv[kMaxWaves];
+    __shared__ int ri[kMaxWaves];
+    __shared__ int s_c;
+    const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    if (frame_masked(d, b)) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
+    const int nwords = (W2 + kDpRun - 1) / kDpRun;
     FrameInfo fi = d.info[b];
     double* tf = d.tab + (int64_t)b * 6 * H;
     double* tvpy = tf + 2 * H;
@@ -597,85 +799,173 @@ __global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* strea
     double* tA = tf + 4 * H;
     double* tB = tf + 5 * H;
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    for (int v = t; v < H; v += kBlock) {
+    for (int v = t; v < H; v += nt) {
         tA[v] = 0.0;
         tB[v] = 0.0;
         d.mxpath[(int64_t)b * H + v] = -1;
     }
     if (fi.flags & LD_FLAG_NOROAD) {
         if (vp_out)
-            for (int v = t; v < H; v += kBlock) {
+            for (int v = t; v < H; v += nt) {
                 vp_out[((int64_t)b * H + v) * 2] = nan;
                 vp_out[((int64_t)b * H + v) * 2 + 1] = nan;
             }
         return;
     }
     const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
-    int* hist = reinterpret_cast<int*>(smem);
-    int* Ea = hist + W2;            // padded by 5 on each side
-    int* Eb = Ea + W2 + 10;
-    int* PX = Eb + W2 + 10;
+    // DP rows and the band histogram are stored run-interleaved, column c at
+    // (c mod 8) * NR + c / 8 + 1, so that the lanes of a wave (one run of 8 columns each)
+    // touch consecutive words; runs -1 and nruns are padding (kBig).
+    const int NR = nwords + 2;
+    const int WP = kDpRun * NR;
+    int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved
+    int* Sa = hist + WP;                 // E << 4
+    int* Sb = Sa + WP;
+    int* PX = Sb + WP;
     int* PY = PX + H;
     int* cur = PY + H;
     int* cur2 = cur + H;
     uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + H);
     const int bm_words = (H + 31) / 32;
-    // edge and vote totals
-    int ne = 0, nv = 0;
-    for (int v = v_h; v <= v_max; ++v) ne += d.rowcnt[(int64_t)b * H + v];
-    for (int v = v_h; v <= v_max; ++v) {
-        const int cnt = d.rowcnt[(int64_t)b * H + v];
-        const ld_edge* e = d.edges + ((int64_t)b * H + v) * d.W;
-        for (int i = t; i < cnt; i += kBlock) nv += e[i].bin >= 0 ? 1 : 0;
+    uint32_t* win = bitmap + bm_words;   // kWalkRows x walk-window words
+    int* cntL = reinterpret_cast<int*>(win + vpx_walk_words_dev(W2));   // per-row edge counts
+    const ld_edge* fedges = d.edges + (int64_t)b * H * d.W;
+    for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
+    for (int i = t; i < WP; i += nt) { hist[i] = 0; Sa[i] = kBig; Sb[i] = kBig; }
+    __syncthreads();
+    int ne = 0;
+    for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
+    ne = block_sum_i32(ne, S.red);
+    int nv = 0;   // votes that landed in a column (counted as each row enters the band)
+    // initial band rows max(v_max - chi, v_h) .. v_max, four rows of loads in flight at a time
+    for (int v = max(v_max - chi, v_h); v <= v_max; v += 4) {
+        int bins[4][kBandPer];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = v + j;
+            band_load(fedges + (int64_t)r * d.W, r <= v_max ? cntL[r] : 0, bins[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int k = 0; k < kBandPer; ++k) nv += bins[j][k] >= 0 ? 1 : 0;
+            band_apply(bins[j], 1, hist, NR);
+        }
     }
-    nv = block_sum_i32(nv, S.red);
-    for (int c = t; c < W2; c += kBlock) hist[c] = 0;
-    for (int c = t; c < 5; c += kBlock) {
-        Ea[c] = kBig; Ea[W2 + 5 + c] = kBig;
-        Eb[c] = kBig; Eb[W2 + 5 + c] = kBig;
+    __syncthreads();
+    for (int c = t; c < W2; c += nt) Sa[ipos(c, NR)] = -hist[ipos(c, NR)] * 16;
+    __syncthreads();
+    const int tau_max = d.P.tau_x_max;
+    const int slope = 16 * d.P.lambda_x + 2;
+    uint32_t* back = reinterpret_cast<uint32_t*>(d.back_x) + (int64_t)b * H * nwords;
+    const int c0 = t * kDpRun;
+    // row-invariant per-thread constants: LDS positions of the window Sh(c0-5 .. c0+12) and
+    // of the own columns in both DP buffers, and the slope offsets slope * c of the window
+    constexpr int kWin = kDpRun + 10;
+    int posA[kWin], posB[kWin], offw[kWin];
+#pragma unroll
+    for (int j = 0; j < kWin; ++j) {
+        posA[j] = WP + ipos(c0 - 5 + j, NR);      // absolute int index of Sa (Sa = smem + WP)
+        posB[j] = posA[j] + WP;                    // Sb = Sa + WP
+        offw[j] = slope * (c0 - 5 + j);
     }
-    __syncthreads();
-    for (int v = max(v_max - chi, v_h); v <= v_max; ++v) band_row(d, b, v, 1, hist);
-    __syncthreads();
-    int* Ec = Ea + 5;
-    int* En = Eb + 5;
-    for (int c = t; c < W2; c += kBlock) Ec[c] = -hist[c];
-    __syncthreads();
-    const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
-    int8_t* back = d.back_x + (int64_t)b * H * W2;
+    const bool full5 = tau_max == 5;
+    // band rows entering / leaving at the next DP row, prefetched one row ahead
+    int nadd[kBandPer], nrem[kBandPer];
+    {
+        const int v = v_max - 1;
+        const int ra = v - chi, rr = v + chi + 1;
+        band_load(fedges + (int64_t)max(ra, 0) * d.W, ra >= v_h ? cntL[ra] : 0, nadd);
+        band_load(fedges + (int64_t)min(rr, v_max) * d.W, rr <= v_max ? cntL[rr] : 0, nrem);
+    }
+    int parity = 0;   // 0: read Sa, write Sb
     for (int v = v_max - 1; v >= v_h; --v) {
-        if (v - chi >= v_h) band_row(d, b, v - chi, 1, hist);
-        if (v + chi + 1 <= v_max) band_row(d, b, v + chi + 1, -1, hist);
+        int cadd[kBandPer], crem[kBandPer];
+#pragma unroll
+        for (int k = 0; k < kBandPer; ++k) { cadd[k] = nadd[k]; crem[k] = nrem[k]; }
+        if (v - 1 >= v_h) {
+            const int ra = v - 1 - chi, rr = v + chi;
+            band_load(fedges + (int64_t)max(ra, 0) * d.W, ra >= v_h ? cntL[ra] : 0, nadd);
+            band_load(fedges + (int64_t)min(rr, v_max) * d.W, rr <= v_max ? cntL[rr] : 0, nrem);
+        }
+#pragma unroll
+        for (int k = 0; k < kBandPer; ++k) nv += cadd[k] >= 0 ? 1 : 0;
+        band_apply(cadd, 1, hist, NR);
+        band_apply(crem, -1, hist, NR);
         __syncthreads();
-        for (int c = t; c < W2; c += kBlock) {
-            int best = Ec[c], bt = 0;
-            for (int a = 1; a <= tau_max; ++a) {
-                const int vl = Ec[c - a] + lam * a;
-                if (vl < best) { best = vl; bt = -a; }
-                const int vr = Ec[c + a] + lam * a;
-                if (vr < best) { best = vr; bt = a; }
+        if (c0 < W2) {
+            int w[kWin], TL[kWin], TR[kWin];
+#pragma unroll
+            for (int j = 0; j < kWin; ++j) {
+                w[j] = smem_i(smem)[parity ? posB[j] : posA[j]];
+                TL[j] = w[j] - offw[j];          // key of tau < 0 minus the per-c constant
+                TR[j] = w[j] + offw[j];          // key of tau > 0 plus the per-c constant
             }
-            En[c] = -hist[c] + best;
-            back[(int64_t)v * W2 + c] = (int8_t)bt;
+            uint32_t word = 0;
+#pragma unroll
+            for (int k = 0; k < kDpRun; ++k) {
+                int lm, rm;
+                if (full5) {
+                    lm = min(min(min(TL[k], TL[k + 1]), min(TL[k + 2], TL[k + 3])), TL[k + 4]);
+                    rm = min(min(min(TR[k + 6], TR[k + 7]), min(TR[k + 8], TR[k + 9])), TR[k + 10]);
+                } else {
+                    lm = kBig; rm = kBig;
+#pragma unroll
+                    for (int a = 1; a <= 5; ++a)
+                        if (a <= tau_max) { lm = min(lm, TL[k + 5 - a]); rm = min(rm, TR[k + 5 + a]); }
+                }
+                const int cc = offw[k + 5];                          // slope * c
+                const int key = min(w[k + 5], min(lm + (cc - 1), rm - cc));
+                const int posc = parity ? posA[k + 5] : posB[k + 5];   // destination buffer
+                if (c0 + k < W2) {
+                    smem_i(smem)[posc] = ((key >> 4) - hist[posA[k + 5] - WP]) * 16;
+                    word |= (uint32_t)(key & 15) << (4 * k);
+                }
+            }
+            back[(int64_t)v * nwords + t] = word;
         }
         __syncthreads();
-        int* tmp = Ec; Ec = En; En = tmp;
+        parity ^= 1;
     }
+    int* Sc = parity ? Sb : Sa;
     int64_t bvv = INT64_MAX;
     int bi = 0x7fffffff;
-    for (int c = t; c < W2; c += kBlock)
-        if ((int64_t)Ec[c] < bvv) { bvv = Ec[c]; bi = c; }
-    block_argmin_i64(bvv, bi, rv, ri);
-    if (t == 0) {
-        int c = bi;
-        for (int v = v_h; v <= v_max; ++v) {
-            d.mxpath[(int64_t)b * H + v] = c;
-            PX[v - v_h] = v;
-            PY[v - v_h] = c - d.half;
-            if (v < v_max) c += back[(int64_t)v * W2 + c];
-        }
+    for (int c = t; c < W2; c += nt) {
+        const int64_t e = Sc[ipos(c, NR)] >> 4;
+        if (e < bvv) { bvv = e; bi = c; }
     }
+    block_argmin_i64(bvv, bi, rv, ri);
+    // backtrace: stage kWalkRows rows of the packed backtrace around the path in LDS, then
+    // one thread follows the path through them
+    if (t == 0) s_c = bi;
     __syncthreads();
+    const int span = 5 * kWalkRows;
+    for (int v0 = v_h; v0 <= v_max; v0 += kWalkRows) {
+        const int c = s_c;
+        const int rows = min(kWalkRows, v_max - v0);          // rows with a backtrace entry
+        const int w0 = max(0, (c - span) / kDpRun), w1 = min(nwords - 1, (c + span) / kDpRun);
+        const int ww = w1 - w0 + 1;
+        for (int i = t; i < rows * ww; i += nt) {
+            const int r = i / ww, k = i % ww;
+            win[i] = back[(int64_t)(v0 + r) * nwords + w0 + k];
+        }
+        __syncthreads();
+        if (t == 0) {
+            int cc = c;
+            const int last = min(v0 + kWalkRows - 1, v_max);
+            for (int v = v0; v <= last; ++v) {
+                d.mxpath[(int64_t)b * H + v] = cc;
+                PX[v - v_h] = v;
+                PY[v - v_h] = cc - d.half;
+                if (v < v_max) {
+                    const uint32_t wd = win[(v - v0) * ww + cc / kDpRun - w0];
+                    cc += rank_to_tau((int)((wd >> (4 * (cc % kDpRun))) & 15u));
+                }
+            }
+            s_c = cc;
+        }
+        __syncthreads();
+    }
     const uint64_t sid = stream_ids ? stream_ids[b] : 0ull;
     const uint64_t fid = frame_idx ? (uint64_t)frame_idx[b] : (uint64_t)b;
     FitRes* fit = d.fit + 2 * b + 1;
@@ -685,12 +975,12 @@ __global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* strea
     const FitRes& g = *fit;
     int bad = v_h - 1;
     if (g.ok) {
-        for (int v = t; v < H; v += kBlock)
+        for (int v = t; v < H; v += nt)
             tvpx[v] = (v >= v_h) ? eval_s<4>(g.coef, g.center, g.kshift, v) : nan;
     }
     __syncthreads();
     if (g.ok) {
-        for (int v = v_h + t; v <= v_max - 1; v += kBlock) {
+        for (int v = v_h + t; v <= v_max - 1; v += nt) {
             const double den = (double)(v + 1) - tvpy[v + 1];
             if (!(den > 0.0)) {
                 bad = max(bad, v);
@@ -701,6 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* strea
         }
     }
     bad = block_max_i32(bad, S.red);
+    nv = block_sum_i32(nv, S.red);
     if (t == 0) {
         fi.flags |= (g.flags & 1) ? LD_FLAG_NOCONS_X : 0;
         if (!g.ok) fi.flags |= LD_FLAG_NOVP;
@@ -711,7 +1002,7 @@ __global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* strea
         d.info[b] = fi;
     }
     if (vp_out) {
-        for (int v = t; v < H; v += kBlock) {
+        for (int v = t; v < H; v += nt) {
             const bool road = v >= v_h && g.ok;
             vp_out[((int64_t)b * H + v) * 2] = road ? tvpx[v] : nan;
             vp_out[((int64_t)b * H + v) * 2 + 1] = v >= v_h ? tvpy[v] : nan;
@@ -720,18 +1011,35 @@ __global__ __launch_bounds__(kBlock) void k_vpx_fit(Dev d, const uint64_t* strea
 }
 
 // ------------------------------------------------------------------------------------------
-// S9 - S12: piecewise weight w_g (Eq. sigma_g), q = G_x w_g, M_0 (box of 3 columns x 7 rows)
-// and M_1 = Sobel-x of M_0 (Alg. "Lane position validation"), and the energy of every
-// candidate along its track (Eq. lane_energy, Eq. lane_visualisation).  One workgroup per
-// frame sweeps the road rows upwards: the q rows of the 7-row box are kept per thread in
-// registers for the NC columns it owns; C (vertical 7-sums), a 3-row M_0 ring and the M_1 row
-// are in LDS.  Each thread carries NT candidates' track position (FP64) and energy.
-__device__ __forceinline__ int mod3(int x) { return ((x % 3) + 3) % 3; }
+// S9 - S12: piecewise weight w_g (Eq. sigma_g), q = G_x w_g, M_0 (box of 3 columns x 7 rows),
+// M_1 = Sobel-x of M_0 (Alg. "Lane position validation"), and the energy of every candidate
+// along its track (Eq. lane_energy, Eq. lane_visualisation).
+//
+// One workgroup per frame.  First q is computed for every road edge (one wave per row) into a
+// per-edge buffer.  Then the road rows are swept upwards: q row v-4 is scattered into a zeroed
+// LDS row, every thread pushes its NC columns into a 9-row register ring (rows v-4..v+4) and
+// forms V(x, v) = sum_y s_y C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0
+// outside the image; a candidate reads M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx)
+// (terms outside the image dropped) at its track column.  Two barriers per row.
+__device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
+    const double tx = (double)(-ed.gy), ty = (double)ed.gx;
+    const double rx = vx - (double)ed.u, ry = vy - (double)r;
+    const double dot = tx * rx + ty * ry;
+    const double tt = tx * tx + ty * ty;
+    const double rr = rx * rx + ry * ry;
+    if (!(dot * dot >= (0.75 * tt) * rr)) return 0.0f;
+    const double cr = tx * ry - ty * rx;
+    const float delta = atan2f((float)fabs(cr), (float)fabs(dot));
+    const float p = delta * (float)(36.0 / 3.14159265358979323846);
+    const float w = sq ? expf(-(p * p) * inv_sg2) : expf(-p * inv_sg2);
+    return (float)ed.gx * w;
+}
 
 template <int NC, int NT>
 __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_mask, float* energy_out) {
     extern __shared__ float fsm[];
-    const int b = blockIdx.x, t = threadIdx.x;
+    const int b = blockIdx.x, t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    if (frame_masked(d, b)) return;
     const int W = d.W, H = d.H, W2 = d.W2, v_max = H - 1;
     const FrameInfo fi = d.info[b];
     double* Eout = d.energy + (int64_t)b * W2;
@@ -742,25 +1050,33 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         }
         return;
     }
-    float* qrow = fsm;               // W
-    float* Crow = qrow + W;          // W
-    float* M0 = Crow + W;            // 3 x W ring
-    float* M1 = M0 + 3 * W;          // W
+    float* qb0 = fsm;                // W, dense q row (ping)
+    float* qb1 = qb0 + W;            // W, dense q row (pong)
+    float* Vp = qb1 + W;             // W + 4: V row with two zero columns on each side
     const double* tf = d.tab + (int64_t)b * 6 * H;
     const double* tvpy = tf + 2 * H;
     const double* tvpx = tf + 3 * H;
     const double* tA = tf + 4 * H;
     const double* tB = tf + 5 * H;
     const int v_h = fi.v_h, v_end = fi.v_end;
-    const double theta_s = 3.14159265358979323846 / 36.0;
     const float inv_sg2 = (float)(1.0 / (d.P.sigma_g * d.P.sigma_g));
     const int sq = d.P.weight_squared;
+    const ld_edge* edges = d.edges + (int64_t)b * H * W;
+    float* qbuf = d.qbuf + (int64_t)b * H * W;
+    const int32_t* rowcnt = d.rowcnt + (int64_t)b * H;
 
-    float ring[NC][7];
+    // q of every road edge, one wave per row
+    for (int r = v_h + wave; r <= v_max; r += kBlock / kWave) {
+        const int cnt = rowcnt[r];
+        const double vx = tvpx[r], vy = tvpy[r];
+        for (int i = lane; i < cnt; i += kWave) qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx, vy, inv_sg2, sq);
+    }
+    for (int i = t; i < 3 * W + 4; i += kBlock) fsm[i] = 0.0f;
+    float ring[NC][9];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int j = 0; j < 7; ++j) ring[k][j] = 0.0f;
+        for (int j = 0; j < 9; ++j) ring[k][j] = 0.0f;
     double uu[NT], ee[NT];
     bool live[NT];
 #pragma unroll
@@ -770,110 +1086,69 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         ee[k] = 0.0;
         live[k] = i < W2 && (cand_mask == nullptr || cand_mask[(int64_t)b * W2 + i] != 0);
     }
-    for (int i = t; i < 3 * W; i += kBlock) M0[i] = 0.0f;
+    __syncthreads();
 
-    // q row r: zero, then scatter the weighted edges of that row
-    auto load_q_row = [&](int r) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int u = t + k * kBlock;
-            if (u < W) qrow[u] = 0.0f;
-        }
-        __syncthreads();
+    auto scatter = [&](int r, float* qb) {
         if (r >= v_h && r <= v_max) {
-            const int cnt = d.rowcnt[(int64_t)b * H + r];
-            const ld_edge* e = d.edges + ((int64_t)b * H + r) * W;
-            const double vx = tvpx[r], vy = tvpy[r];
-            for (int i = t; i < cnt; i += kBlock) {
-                const ld_edge ed = e[i];
-                const double tx = (double)(-ed.gy), ty = (double)ed.gx;
-                const double rx = vx - (double)ed.u, ry = vy - (double)r;
-                const double dot = tx * rx + ty * ry;
-                const double tt = tx * tx + ty * ty;
-                const double rr = rx * rx + ry * ry;
-                float q = 0.0f;
-                if (dot * dot >= (0.75 * tt) * rr) {
-                    const double cr = tx * ry - ty * rx;
-                    const float delta = atan2f((float)fabs(cr), (float)fabs(dot));
-                    const float p = delta / (float)theta_s;
-                    const float w = sq ? expf(-(p * p) * inv_sg2) : expf(-p * inv_sg2);
-                    q = (float)ed.gx * w;
-                }
-                qrow[ed.u] = q;
-            }
+            const int cnt = rowcnt[r];
+            for (int i = t; i < cnt; i += kBlock) qb[edges[(int64_t)r * W + i].u] = qbuf[(int64_t)r * W + i];
         }
-        __syncthreads();
     };
-    // push q row into the register ring (slot 0 = newest = lowest row)
-    auto push_ring = [&]() {
+    auto push = [&](float* qb) {   // slot 0 = newest row; reads and re-zeroes the owned columns
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
 #pragma unroll
-            for (int j = 6; j > 0; --j) ring[k][j] = ring[k][j - 1];
-            ring[k][0] = (u < W) ? qrow[u] : 0.0f;
+            for (int j = 8; j > 0; --j) ring[k][j] = ring[k][j - 1];
+            ring[k][0] = 0.0f;
+            if (u < W) { ring[k][0] = qb[u]; qb[u] = 0.0f; }
         }
     };
-    // preload q rows v_max, v_max-1, v_max-2 (rows below the image are zero)
-    for (int r = v_max; r >= v_max - 2; --r) {
-        load_q_row(r);
-        push_ring();
+    int p = 0;
+    for (int r = v_max; r >= v_max - 3; --r) {     // rows below the image are zero
+        float* qb = p ? qb1 : qb0;
+        scatter(r, qb);
+        __syncthreads();
+        push(qb);
+        p ^= 1;
     }
-    for (int m = v_max; m >= v_end - 1; --m) {
-        // q row m-3 enters; the ring then holds q rows m-3 .. m+3
-        load_q_row(m - 3);
-        push_ring();
+    for (int v = v_max; v >= v_end; --v) {
+        float* qb = p ? qb1 : qb0;
+        scatter(v - 4, qb);
+        __syncthreads();
+        push(qb);
+        p ^= 1;
+        // the ring holds q rows v-4 (slot 0) .. v+4 (slot 8)
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
             if (u < W) {
-                float c = ring[k][0];
-#pragma unroll
-                for (int j = 1; j < 7; ++j) c += ring[k][j];
-                Crow[u] = c;
+                const float* r = ring[k];
+                const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
+                const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
+                const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
+                const float cp1 = (s5 + r[7]) + r[8];   // C(v+1): rows v-2..v+4
+                float V = 2.0f * c0;
+                if (v >= 1) V += cm1;                   // M_0 is zero outside the image rows
+                if (v + 1 <= v_max) V += cp1;
+                Vp[u + 2] = V;
             }
         }
         __syncthreads();
-        float* M0m = M0 + mod3(m) * W;
+        const double A = v < v_max ? tA[v] : 0.0, Bc = v < v_max ? tB[v] : 0.0;
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int u = t + k * kBlock;
-            if (u < W) {
-                const float l = u > 0 ? Crow[u - 1] : 0.0f;
-                const float rr = u < W - 1 ? Crow[u + 1] : 0.0f;
-                M0m[u] = (m >= 0 && m <= v_max) ? (l + Crow[u]) + rr : 0.0f;   // zero outside the image
-            }
-        }
-        __syncthreads();
-        const int kr = m + 1;   // M_1 row
-        if (kr <= v_max) {
-            const float* Ma = M0 + mod3(kr - 1) * W;                  // row kr-1 (= m)
-            const float* Mb = M0 + mod3(kr) * W;                      // row kr
-            const bool has_c = kr + 1 <= v_max;
-            const float* Mc = M0 + mod3(kr + 1) * W;                  // row kr+1
-#pragma unroll
-            for (int k = 0; k < NC; ++k) {
-                const int u = t + k * kBlock;
-                if (u < W) {
-                    float ra = 0.0f, rb = 0.0f, rc = 0.0f;
-                    if (u + 1 < W) { ra += Ma[u + 1]; rb += Mb[u + 1]; rc += has_c ? Mc[u + 1] : 0.0f; }
-                    if (u >= 1) { ra -= Ma[u - 1]; rb -= Mb[u - 1]; rc -= has_c ? Mc[u - 1] : 0.0f; }
-                    M1[u] = (ra + 2.0f * rb) + rc;
+        for (int k = 0; k < NT; ++k) {
+            if (live[k]) {
+                if (v < v_max) uu[k] = fma(Bc, uu[k], A);
+                const double x = uu[k] + 0.5;
+                if (x >= 0.0 && x < (double)W) {
+                    const int col = (int)floor(x);
+                    float m1 = 0.0f;
+                    if (col + 1 <= W - 1) m1 += (Vp[col + 2] + Vp[col + 3]) + Vp[col + 4];
+                    if (col >= 1) m1 -= (Vp[col] + Vp[col + 1]) + Vp[col + 2];
+                    ee[k] += (double)m1;
                 }
             }
-            __syncthreads();
-            if (kr >= v_end) {
-                const double A = kr < v_max ? tA[kr] : 0.0, Bc = kr < v_max ? tB[kr] : 0.0;
-#pragma unroll
-                for (int k = 0; k < NT; ++k) {
-                    if (live[k]) {
-                        if (kr < v_max) uu[k] = fma(Bc, uu[k], A);
-                        const double x = uu[k] + 0.5;
-                        if (x >= 0.0 && x < (double)W) ee[k] += (double)M1[(int)floor(x)];
-                    }
-                }
-            }
-            __syncthreads();
         }
     }
 #pragma unroll
@@ -891,12 +1166,13 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
 // of minima within d_nms of a deeper accepted one; lane curves by iterating the track.
 __global__ __launch_bounds__(kBlock) void k_peaks(Dev d, ld_lanes* lanes_out, float* curves_out) {
     extern __shared__ unsigned char smem[];
-    __shared__ int64_t rv[kWaves];
-    __shared__ int ri[kWaves];
-    __shared__ double dred[kWaves];
+    __shared__ int64_t rv[kMaxWaves];
+    __shared__ int ri[kMaxWaves];
+    __shared__ double dred[kMaxWaves];
     __shared__ int acc[LD_MAX_LANES];
     __shared__ int s_nacc;
     const int b = blockIdx.x, t = threadIdx.x;
+    if (frame_masked(d, b)) return;
     const int W2 = d.W2, H = d.H, v_max = H - 1;
     const FrameInfo fi = d.info[b];
     const double* E = d.energy + (int64_t)b * W2;
@@ -909,7 +1185,7 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Dev d, ld_lanes* lanes_out, fl
     if (lane_id() == 0) dred[t / kWave] = mn;
     __syncthreads();
     mn = dred[0];
-    for (int w = 1; w < kWaves; ++w) mn = fmin(mn, dred[w]);
+    for (int w = 1; w < nwaves(); ++w) mn = fmin(mn, dred[w]);
     const bool any = !(fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP)) && mn < 0.0;
     const double thr = d.P.rho_lpv * mn;
     for (int i = t; i < W2; i += kBlock) {
@@ -1036,20 +1312,68 @@ struct ProfScope {
     }
 };
 
+int vdisp_fit_threads(const Dev& d) {
+    return std::min(1024, std::max(256, ((d.H + kVdRows - 1) / kVdRows + 63) / 64 * 64));
+}
+
 size_t vdisp_fit_lds(const Dev& d) {
-    return sizeof(int) * (2 * (size_t)d.H + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32);
+    return sizeof(int) * (2 * (size_t)d.H + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32) +
+           (size_t)kVdWalk * kVdWalkCols;
+}
+
+int vpx_fit_threads(const Dev& d) {
+    const int runs = (d.W2 + kDpRun - 1) / kDpRun;
+    return std::min(1024, std::max(64, (runs + 63) / 64 * 64));
 }
 
 size_t vpx_fit_lds(const Dev& d) {
-    return sizeof(int) * ((size_t)d.W2 + 2 * ((size_t)d.W2 + 10) + 4 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
+    const size_t WP = (size_t)kDpRun * ((d.W2 + kDpRun - 1) / kDpRun + 2);
+    return sizeof(int) * (3 * WP + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32 + (size_t)vpx_walk_words_dev(d.W2));
 }
 
-size_t energy_lds(const Dev& d) { return sizeof(float) * 6 * (size_t)d.W; }
+size_t energy_lds(const Dev& d) { return sizeof(float) * (3 * (size_t)d.W + 4); }
 
+// Raise a kernel's dynamic LDS limit once per size (later launches, including those recorded
+// into a captured graph, issue nothing but the launch).
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 32 * 1024)
-        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    static size_t granted = 0;   // one counter per kernel instantiation
+    if (bytes > 32 * 1024 && bytes > granted) {
+        if (hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+            granted = bytes;
+        else
+            (void)hipGetLastError();
+    }
+}
+
+constexpr int kRegions = 14;
+
+// Byte offsets and sizes of the regions of one frame object's device allocation.
+size_t frame_layout(int width, int height, int batch, int d_max, size_t* off, size_t* sz) {
+    const size_t B = (size_t)batch, H = (size_t)height, W = (size_t)width, D1 = (size_t)d_max + 1, W2 = 2 * (size_t)width;
+    const size_t s[kRegions] = {
+        B * D1 * H * 4,                 // myT
+        B * D1 * H,                     // back_y
+        B * 2 * D1 * 4,                 // my_pts
+        B * 2 * sizeof(FitRes),         // fit
+        B * sizeof(FrameInfo),          // info
+        B * 6 * H * 8,                  // tab
+        B * H * 4,                      // rowcnt
+        B * H * W * sizeof(ld_edge),    // edges
+        B * H * ((W2 + kDpRun - 1) / kDpRun) * 4,   // back_x (4 bits per column)
+        B * H * 4,                      // mxpath
+        B * W2 * 8,                     // energy
+        B * 6 * kMaxRounds * 4,         // trace
+        B * H * W * 4,                  // qbuf
+        B * H * 2 * 4,                  // rbound
+    };
+    size_t o = 0;
+    for (int i = 0; i < kRegions; ++i) {
+        sz[i] = s[i];
+        off[i] = o;
+        o += align_up(s[i]);
+    }
+    return o;
 }
 
 ld_status check_params(const ld_params& p) {
@@ -1063,24 +1387,36 @@ ld_status check_params(const ld_params& p) {
     return LD_OK;
 }
 
+template <int FMT>
+void launch_hist(int npt, dim3 g, size_t lds, hipStream_t st, const Dev& d, const uint8_t* dp, int64_t pitch,
+                 int32_t* out) {
+    if (npt <= 1) hipLaunchKernelGGL((k_vdisp_hist<FMT, 1>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+    else if (npt <= 2) hipLaunchKernelGGL((k_vdisp_hist<FMT, 2>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+    else if (npt <= 4) hipLaunchKernelGGL((k_vdisp_hist<FMT, 4>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+    else if (npt <= 5) hipLaunchKernelGGL((k_vdisp_hist<FMT, 5>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+    else if (npt <= 8) hipLaunchKernelGGL((k_vdisp_hist<FMT, 8>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+    else hipLaunchKernelGGL((k_vdisp_hist<FMT, 16>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
+}
+
 ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t* sid, const int64_t* fidx,
                     int32_t* vdisp_out, double* beta_out, hipStream_t st) {
     Dev& d = f->d;
-    dim3 g1((d.H + kHistRows - 1) / kHistRows, f->active);
-    const size_t l1 = sizeof(int) * kHistRows * d.D1;
+    dim3 g1((d.H + d.hist_rows - 1) / d.hist_rows, f->active);
+    const size_t l1 = sizeof(int) * d.hist_rows * d.D1;
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
     {
         ProfScope ps(f, 0, st);
-        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U8>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
-        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_F32>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
-        else hipLaunchKernelGGL(k_vdisp_hist<LD_DISP_U16Q4>, g1, dim3(kBlock), l1, st, d, dp, pitch, vdisp_out);
+        const int npt = (d.W + kBlock - 1) / kBlock;
+        if (d.fmt == LD_DISP_U8) launch_hist<LD_DISP_U8>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
+        else if (d.fmt == LD_DISP_F32) launch_hist<LD_DISP_F32>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
+        else launch_hist<LD_DISP_U16Q4>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
     }
     if (launch_ok() != LD_OK) return LD_E_HIP;
     const size_t l2 = vdisp_fit_lds(d);
     allow_lds(k_vdisp_fit, l2);
     {
         ProfScope ps(f, 1, st);
-        hipLaunchKernelGGL(k_vdisp_fit, dim3(f->active), dim3(kBlock), l2, st, d, sid, fidx, beta_out);
+        hipLaunchKernelGGL(k_vdisp_fit, dim3(f->active), dim3(vdisp_fit_threads(d)), l2, st, d, sid, fidx, beta_out);
     }
     return launch_ok();
 }
@@ -1088,20 +1424,26 @@ ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t*
 ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, const uint64_t* sid,
                  const int64_t* fidx, const double* seed_gamma, double* vp_out, hipStream_t st) {
     Dev& d = f->d;
-    dim3 g3((d.W + kBlock - 1) / kBlock, (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
+    dim3 g3((d.W + 4 * kQT - 1) / (4 * kQT), (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
     {
         ProfScope ps(f, 2, st);
-        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
-        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
-        else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kBlock), 0, st, d, grey, gp, dp, dpt);
+        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+        else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
     }
     if (launch_ok() != LD_OK) return LD_E_HIP;
     const size_t l4 = vpx_fit_lds(d);
-    allow_lds(k_vpx_fit, l4);
+    const int nt4 = vpx_fit_threads(d);
     {
         ProfScope ps(f, 3, st);
-        hipLaunchKernelGGL(k_vpx_fit, dim3(f->active), dim3(kBlock), l4, st, d, sid, fidx, seed_gamma, vp_out);
+        if (nt4 <= 512) {
+            allow_lds(k_vpx_fit<512>, l4);
+            hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
+        } else {
+            allow_lds(k_vpx_fit<1024>, l4);
+            hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
+        }
     }
     return launch_ok();
 }
@@ -1116,9 +1458,14 @@ void launch_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st)
 ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
     ProfScope ps(f, 4, st);
     const int nc = (f->d.W + kBlock - 1) / kBlock;
-    if (nc <= 2) launch_energy<2, 4>(f, mask, eout, st);
+    if (nc <= 1) launch_energy<1, 2>(f, mask, eout, st);
+    else if (nc <= 2) launch_energy<2, 4>(f, mask, eout, st);
+    else if (nc <= 3) launch_energy<3, 6>(f, mask, eout, st);
     else if (nc <= 4) launch_energy<4, 8>(f, mask, eout, st);
+    else if (nc <= 5) launch_energy<5, 10>(f, mask, eout, st);
+    else if (nc <= 6) launch_energy<6, 12>(f, mask, eout, st);
     else if (nc <= 8) launch_energy<8, 16>(f, mask, eout, st);
+    else if (nc <= 12) launch_energy<12, 24>(f, mask, eout, st);
     else launch_energy<16, 32>(f, mask, eout, st);
     return launch_ok();
 }
@@ -1156,6 +1503,7 @@ const char* ld_status_string(ld_status s) {
         case LD_E_NOMEM: return "out of device memory";
         case LD_E_HIP: return "HIP runtime error";
         case LD_E_STATE: return "step called out of order";
+        case LD_E_BUSY: return "queue full, retry later";
     }
     return "unknown status";
 }
@@ -1170,28 +1518,17 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
     ld_params_default(&P);
     if (p) P = *p;
     if (check_params(P) != LD_OK) return LD_E_INVAL;
+    // the row DP keeps (E << 4 | rank) in int32: E >= -width * height * (2 chi + 1)
+    if ((int64_t)width * height * (2 * (int64_t)P.chi + 1) + 5 * (int64_t)P.lambda_x >= ((int64_t)1 << 27)) return LD_E_INVAL;
     ld_frame f = new (std::nothrow) ld_frame_s();
     if (!f) return LD_E_NOMEM;
     Dev& d = f->d;
     d.W = width; d.H = height; d.D1 = d_max + 1; d.W2 = 2 * width; d.half = width / 2; d.fmt = fmt;
     d.d_max = d_max; d.B = batch; d.P = P;
-    const size_t B = (size_t)batch, H = (size_t)height, W = (size_t)width, D1 = (size_t)d.D1, W2 = (size_t)d.W2;
-    size_t off[12], o = 0;
-    size_t sz[12] = {
-        B * D1 * H * 4,                 // myT
-        B * D1 * H,                     // back_y
-        B * 2 * D1 * 4,                 // my_pts
-        B * 2 * sizeof(FitRes),         // fit
-        B * sizeof(FrameInfo),          // info
-        B * 6 * H * 8,                  // tab
-        B * H * 4,                      // rowcnt
-        B * H * W * sizeof(ld_edge),    // edges
-        B * H * W2,                     // back_x
-        B * H * 4,                      // mxpath
-        B * W2 * 8,                     // energy
-        B * 6 * kMaxRounds * 4,         // trace
-    };
-    for (int i = 0; i < 12; ++i) { off[i] = o; o += align_up(sz[i]); }
+    d.hist_rows = std::max(kHistGroup, std::min(32, (8192 / d.D1) / kHistGroup * kHistGroup));
+    size_t off[kRegions], sz[kRegions];
+    const size_t o = frame_layout(width, height, batch, d_max, off, sz);
+
     if (hipGetDevice(&f->device) != hipSuccess) { delete f; return LD_E_HIP; }
     if (hipMalloc(&f->mem, o) != hipSuccess) { (void)hipGetLastError(); delete f; return LD_E_NOMEM; }
     f->mem_bytes = o;
@@ -1208,6 +1545,8 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
     d.mxpath = reinterpret_cast<int32_t*>(base + off[9]);
     d.energy = reinterpret_cast<double*>(base + off[10]);
     d.trace = reinterpret_cast<int32_t*>(base + off[11]);
+    d.qbuf = reinterpret_cast<float*>(base + off[12]);
+    d.rbound = reinterpret_cast<uint32_t*>(base + off[13]);
     // small state starts zeroed so that introspection of an unprocessed frame is defined
     if (hipMemset(d.info, 0, sz[4]) != hipSuccess || hipMemset(d.trace, 0xff, sz[11]) != hipSuccess ||
         hipMemset(d.fit, 0, sz[3]) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -1215,6 +1554,7 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
         delete f;
         return LD_E_HIP;
     }
+    d.nact = nullptr;
     f->batch = batch;
     f->active = batch;
     f->last = nullptr;
@@ -1366,3 +1706,18 @@ ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t 
 }
 
 }  // extern "C"
+
+// ==========================================================================================
+// Internal hooks for the serving layer (ld_server.hip); not part of the C ABI.
+ld_status ldi_frame_bind_count(ld_frame f, const int32_t* d_count) {
+    if (!f) return LD_E_INVAL;
+    f->d.nact = d_count;
+    return LD_OK;
+}
+
+const ld_fit* ldi_frame_fits(ld_frame f) { return f ? reinterpret_cast<const ld_fit*>(f->d.fit) : nullptr; }
+
+size_t ldi_frame_bytes(int32_t width, int32_t height, int32_t batch, int32_t d_max) {
+    size_t off[kRegions], sz[kRegions];
+    return frame_layout(width, height, batch, d_max, off, sz);
+}

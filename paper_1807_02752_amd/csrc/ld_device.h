@@ -15,8 +15,8 @@ typedef __int128 i128;
 typedef unsigned __int128 u128;
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;          // threads of every per-frame workgroup
-constexpr int kWaves = kBlock / kWave;
+constexpr int kBlock = 256;          // default workgroup size
+constexpr int kMaxWaves = 16;        // up to 1024 threads per workgroup
 constexpr int kMaxHyp = 64;          // one RANSAC hypothesis per lane of a wave
 
 // ------------------------------------------------------------------------ wave helpers

@@ -15,7 +15,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libld.so")
 
-LD_OK, LD_E_INVAL, LD_E_NOMEM, LD_E_HIP, LD_E_STATE = 0, -1, -2, -3, -4
+LD_OK, LD_E_INVAL, LD_E_NOMEM, LD_E_HIP, LD_E_STATE, LD_E_BUSY = 0, -1, -2, -3, -4, -5
+LD_MAX_CLASSES = 4
 LD_DISP_U8, LD_DISP_F32, LD_DISP_U16Q4 = 0, 1, 2
 LD_FLAG_NOROAD, LD_FLAG_NOVP, LD_FLAG_NOCONS_Y, LD_FLAG_NOCONS_X, LD_FLAG_FALLBACK = 1, 2, 4, 8, 16
 LD_MAX_LANES = 16
@@ -47,6 +48,19 @@ class ld_fit(C.Structure):
     _fields_ = [("ok", C.c_int32), ("flags", C.c_int32), ("center", C.c_int32), ("kshift", C.c_int32),
                 ("rounds", C.c_int32), ("n_survivors", C.c_int32),
                 ("coef", C.c_double * 5), ("raw", C.c_double * 5)]
+
+
+class ld_server_config(C.Structure):
+    _fields_ = [("n_classes", C.c_int32), ("width", C.c_int32 * LD_MAX_CLASSES), ("height", C.c_int32 * LD_MAX_CLASSES),
+                ("fmt", C.c_int32 * LD_MAX_CLASSES), ("d_max", C.c_int32 * LD_MAX_CLASSES),
+                ("max_batch", C.c_int32 * LD_MAX_CLASSES), ("n_streams", C.c_int32), ("inflight", C.c_int32),
+                ("max_queue", C.c_int32), ("use_graphs", C.c_int32), ("seed_from_state", C.c_int32),
+                ("hbm_budget", C.c_int64)]
+
+
+class ld_server_result(C.Structure):
+    _fields_ = [("request", C.c_int64), ("stream_id", C.c_int32), ("cls", C.c_int32), ("frame_idx", C.c_int64),
+                ("t_submit", C.c_double), ("t_done", C.c_double), ("lanes", ld_lanes)]
 
 
 LANES_DTYPE = np.dtype([("n", "<i4"), ("flags", "<i4"), ("v_h", "<i4"), ("v_end", "<i4"),
@@ -87,8 +101,15 @@ def lib():
         L.ld_status_string.restype = C.c_char_p
         L.ld_frame_read.argtypes = [vp, i32, i32, vp, i64, vp]
         L.ld_frame_profile.argtypes = [vp, i32]
+        L.ld_server_create.argtypes = [C.POINTER(ld_server_config), C.POINTER(ld_params), C.POINTER(vp)]
+        L.ld_server_destroy.argtypes = [vp]
+        L.ld_server_submit.argtypes = [vp, i32, i32, vp, i64, vp, i64, C.POINTER(C.c_int64)]
+        L.ld_server_poll.argtypes = [vp, C.POINTER(ld_server_result), i32, C.POINTER(C.c_int32)]
+        L.ld_server_pending.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.ld_server_engines.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.ld_frame_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
-        for name in ("ld_frame_profile", "ld_frame_kernel_times", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
+        for name in ("ld_server_create", "ld_server_destroy", "ld_server_submit", "ld_server_poll",
+                     "ld_server_pending", "ld_server_engines", "ld_frame_profile", "ld_frame_kernel_times", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
                      "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_frame_read"):
             getattr(L, name).restype = i32
         _lib = L
@@ -97,7 +118,8 @@ def lib():
 
 EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp",
             "ld_vp_ransac", "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_status_string",
-            "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times"]
+            "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times", "ld_server_create", "ld_server_destroy",
+            "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks"]
 
 
@@ -175,6 +197,104 @@ def ld_frame_profile(f, enable):
 
 def ld_frame_kernel_times(f, ms_out, calls_out, n):
     return lib().ld_frame_kernel_times(f, ms_out, calls_out, n)
+
+
+def ld_server_create(cfg, params=None):
+    h = C.c_void_p()
+    st = lib().ld_server_create(C.byref(cfg), C.byref(params) if params is not None else None, C.byref(h))
+    return st, h
+
+
+def ld_server_destroy(s):
+    return lib().ld_server_destroy(s)
+
+
+def ld_server_submit(s, stream_id, cls, grey, grey_pitch, disp, disp_pitch):
+    req = C.c_int64(-1)
+    st = lib().ld_server_submit(s, stream_id, cls, grey, grey_pitch, disp, disp_pitch, C.byref(req))
+    return st, req.value
+
+
+def ld_server_poll(s, results, max_results):
+    n = C.c_int32(0)
+    st = lib().ld_server_poll(s, results, max_results, C.byref(n))
+    return st, n.value
+
+
+def ld_server_pending(s):
+    q, f = C.c_int32(0), C.c_int32(0)
+    st = lib().ld_server_pending(s, C.byref(q), C.byref(f))
+    return st, q.value, f.value
+
+
+def ld_server_engines(s):
+    pc = (C.c_int32 * LD_MAX_CLASSES)()
+    b = C.c_int64(0)
+    st = lib().ld_server_engines(s, pc, C.byref(b))
+    return st, list(pc), b.value
+
+
+def server_config(classes, *, n_streams=32, inflight=2, max_queue=256, use_graphs=True, seed_from_state=True,
+                  hbm_budget=64 << 30):
+    """classes: list of (width, height, fmt, d_max, max_batch)."""
+    cfg = ld_server_config()
+    cfg.n_classes = len(classes)
+    for k, (w, h, f, dm, mb) in enumerate(classes):
+        cfg.width[k], cfg.height[k], cfg.fmt[k], cfg.d_max[k], cfg.max_batch[k] = w, h, f, dm, mb
+    cfg.n_streams, cfg.inflight, cfg.max_queue = n_streams, inflight, max_queue
+    cfg.use_graphs, cfg.seed_from_state, cfg.hbm_budget = int(use_graphs), int(seed_from_state), int(hbm_budget)
+    return cfg
+
+
+class Server:
+    """Continuous-batching server (ld_server_*).  Frames are torch CUDA tensors [H, W] that
+    the caller keeps alive until their result has been returned by poll()."""
+
+    def __init__(self, cfg, params=None):
+        self.cfg = cfg
+        st, h = ld_server_create(cfg, params)
+        check(st, "ld_server_create")
+        self.handle = h
+        self._buf = (ld_server_result * 256)()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ld_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, stream_id, cls, grey, disp):
+        st, req = ld_server_submit(self.handle, stream_id, cls, C.c_void_p(grey.data_ptr()),
+                                   grey.stride(-2) * grey.element_size(), C.c_void_p(disp.data_ptr()),
+                                   disp.stride(-2) * disp.element_size())
+        return st, req
+
+    def poll(self):
+        st, n = ld_server_poll(self.handle, self._buf, len(self._buf))
+        check(st, "ld_server_poll")
+        out = []
+        for i in range(n):
+            r = self._buf[i]
+            L = r.lanes
+            out.append({"request": r.request, "stream": r.stream_id, "cls": r.cls, "frame_idx": r.frame_idx,
+                        "t_submit": r.t_submit, "t_done": r.t_done, "n": L.n, "flags": L.flags, "v_h": L.v_h,
+                        "v_end": L.v_end, "u_start": list(L.u_start[: L.n]), "energy": list(L.energy[: L.n])})
+        return out
+
+    def pending(self):
+        st, q, f = ld_server_pending(self.handle)
+        check(st, "ld_server_pending")
+        return q, f
+
+    def engines(self):
+        st, pc, b = ld_server_engines(self.handle)
+        check(st, "ld_server_engines")
+        return pc, b
 
 
 # ---------------------------------------------------------------------------- torch front end

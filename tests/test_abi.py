@@ -66,3 +66,16 @@ def test_product_path_never_touches_the_oracle():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
                 assert "ldref" not in txt, fn
+
+
+def test_server_config_validation_without_device(L):
+    from paper_1807_02752_amd import ld
+    for bad in [dict(classes=[]), dict(classes=[(4, 96, 0, 48, 4)]), dict(classes=[(320, 96, 7, 48, 4)]),
+                dict(classes=[(320, 96, 0, 48, 0)]), dict(classes=[(320, 96, 0, 48, 4)], inflight=0),
+                dict(classes=[(320, 96, 0, 48, 4)], max_queue=0)]:
+        classes = bad.pop("classes")
+        cfg = ld.server_config(classes, **bad)
+        st, h = ld.ld_server_create(cfg)
+        assert st == ld.LD_E_INVAL and not h.value
+    assert ld.ld_server_destroy(None) == ld.LD_OK
+    assert ld.ld_server_submit(None, 0, 0, None, 0, None, 0)[0] == ld.LD_E_INVAL

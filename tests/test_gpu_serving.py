@@ -1,0 +1,148 @@
+"""Serving: continuous batching over many streams gives each frame the result it gets alone.
+
+Every frame that goes through the server (mixed resolution classes, several streams
+interleaved, batches formed as requests arrive, graph replays or eager launches) must
+match, lane for lane, the same frame run on its own through the frame-object API in stream
+order with the stream's previous V_px fit as RANSAC seed; that sequential chain is checked
+against the CPU oracle with the same seeds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_02752_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CLASSES = [(320, 96, 0, 48, 4), (640, 192, 0, 96, 3)]
+
+
+def _ld():
+    from paper_1807_02752_amd import ld
+    return ld
+
+
+def _frames(n_streams, per_stream):
+    """stream s -> list of (grey, disp, cls) frames; classes alternate by stream."""
+    out = {}
+    for s in range(n_streams):
+        cls = s % len(CLASSES)
+        W, H, _, dm, _ = CLASSES[cls]
+        out[s] = [(*synth.make_scaled_c1(W, H, dm, seed=100 + s, idx=i)[:2], cls) for i in range(per_stream)]
+    return out
+
+
+def _sequential(frames, s):
+    """One stream alone, frame by frame, seeded with its previous fit (NaN: none)."""
+    ld = _ld()
+    res, seed = [], np.full(5, np.nan)
+    for k, (g, d, cls) in enumerate(frames):
+        W, H, fmt, dm, _ = CLASSES[cls]
+        det = ld.Detector(W, H, 1, fmt, dm)
+        gt = torch.from_numpy(g[None]).cuda()
+        dt = torch.from_numpy(d[None]).cuda()
+        sid = torch.tensor([s], dtype=torch.int64).cuda()
+        fid = torch.tensor([k], dtype=torch.int64).cuda()
+        sg = torch.from_numpy(seed[None].copy()).cuda()
+        lanes = det.lanes_buffer()
+        det.vdisp(dt, stream_ids=sid, frame_idx=fid)
+        det.vp_ransac(gt, dt, stream_ids=sid, frame_idx=fid, seed_gamma=sg)
+        det.lane_energy()
+        det.peaks(lanes)
+        det.sync()
+        L = ld.Detector.parse_lanes(lanes)[0]
+        gam = det.read(ld.LD_STATE_GAMMA, 0)[0]
+        if gam["ok"]:
+            seed = np.array(gam["raw"], dtype=np.float64)
+        res.append((int(L["n"]), int(L["flags"]), list(L["u_start"][: L["n"]]), list(L["energy"][: L["n"]])))
+        det.close()
+    return res
+
+
+def _serve(frames, use_graphs, order):
+    ld = _ld()
+    cfg = ld.server_config(CLASSES, n_streams=len(frames), inflight=2, max_queue=64, use_graphs=use_graphs)
+    srv = ld.Server(cfg)
+    keep = []
+    got = {s: {} for s in frames}
+    pos = {s: 0 for s in frames}
+    for s in order:
+        g, d, cls = frames[s][pos[s]]
+        gt, dt = torch.from_numpy(g).cuda(), torch.from_numpy(d).cuda()
+        keep.append((gt, dt))
+        st, _ = srv.submit(s, cls, gt, dt)
+        assert st == ld.LD_OK
+        pos[s] += 1
+        for r in srv.poll():                       # requests arrive while others run
+            got[r["stream"]][r["frame_idx"]] = r
+    for _ in range(100000):
+        q, f = srv.pending()
+        for r in srv.poll():
+            got[r["stream"]][r["frame_idx"]] = r
+        if q == 0 and f == 0:
+            break
+    srv.close()
+    return got
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_equals_each_frame_alone(use_graphs):
+    frames = _frames(5, 4)
+    rng = np.random.default_rng(1)
+    order = [s for s in frames for _ in range(len(frames[s]))]
+    rng.shuffle(order)
+    got = _serve(frames, use_graphs, order)
+    for s in frames:
+        want = _sequential(frames[s], s)
+        assert sorted(got[s]) == list(range(len(frames[s])))
+        for k, (n, flags, us, es) in enumerate(want):
+            r = got[s][k]
+            assert (r["n"], r["flags"], r["u_start"]) == (n, flags, us), (s, k)
+            assert r["energy"] == es
+            assert r["t_done"] >= r["t_submit"]
+
+
+def test_sequential_seeded_chain_matches_oracle():
+    frames = _frames(2, 3)
+    for s in frames:
+        want = _sequential(frames[s], s)
+        seed = None
+        for k, (g, d, cls) in enumerate(frames[s]):
+            dm = CLASSES[cls][3]
+            r = oracle.detect(g, d, dm, stream_id=s, frame_idx=k,
+                              seed_gamma=np.full(5, np.nan) if seed is None else seed)
+            assert (want[k][0], want[k][1], want[k][2]) == (r.n_lanes, r.flags, list(r.u_start)), (s, k)
+            if r.gamma.ok:
+                seed = np.array(r.gamma.raw[:5])
+
+
+def test_server_admission_by_budget_and_queue():
+    ld = _ld()
+    W, H, fmt, dm, mb = CLASSES[0]
+    W2, H2, fmt2, dm2, mb2 = CLASSES[1]
+    probe = ld.Server(ld.server_config([CLASSES[0]], n_streams=4, inflight=1, use_graphs=False))
+    _, one = probe.engines()
+    probe.close()
+    # budget for one small-class engine only: the large class admits nothing
+    cfg = ld.server_config([CLASSES[0], CLASSES[1]], n_streams=4, inflight=2, max_queue=2, use_graphs=False,
+                           hbm_budget=one + 1024)
+    srv = ld.Server(cfg)
+    per_class, used = srv.engines()
+    assert per_class[:2] == [1, 0] and used <= one + 1024
+    g, d = synth.make_scaled_c1(W, H, dm, seed=5, idx=0)[:2]
+    gt, dt = torch.from_numpy(g).cuda(), torch.from_numpy(d).cuda()
+    g2, d2 = synth.make_scaled_c1(W2, H2, dm2, seed=5, idx=0)[:2]
+    gt2, dt2 = torch.from_numpy(g2).cuda(), torch.from_numpy(d2).cuda()
+    assert srv.submit(1, 1, gt2, dt2)[0] == ld.LD_E_NOMEM
+    assert srv.submit(0, 0, gt, dt)[0] == ld.LD_OK
+    assert srv.submit(0, 0, gt, dt)[0] == ld.LD_OK
+    assert srv.submit(2, 0, gt, dt)[0] == ld.LD_E_BUSY           # max_queue = 2
+    done = []
+    for _ in range(100000):
+        done += srv.poll()
+        if len(done) == 2:
+            break
+    assert [r["frame_idx"] for r in done] == [0, 1]               # one stream: in order, one at a time
+    assert srv.submit(2, 0, gt, dt)[0] == ld.LD_OK
+    srv.close()
