@@ -47,6 +47,27 @@ def make_workload(n_seq: int, per_seq: int, procs: int):
     return np.concatenate(greys), np.concatenate(disps)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "lane_path_1242x375_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in ("ld.hip", "ld_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1807_02752_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"].get(kernel)
+
+
 def cpu_baseline(greys, disps, seconds: float, threads: int):
     """The oracle, as it stands, on the host cores: frames split over `threads` threads
     (ctypes releases the GIL during each call)."""
@@ -83,6 +104,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (4 launches) to calibrate HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +115,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calib > 0:
+        n = args.copy_calib << 18
+        src = torch.arange(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            torch.mul(src, 1.0, out=dst)       # one elementwise kernel: reads and writes 4n bytes
+        torch.cuda.synchronize()
+        log(f"copy calibration: 4 launches of {4 * n} B read + {4 * n} B written")
+        return
     from paper_1807_02752_amd import ld
 
     t0 = time.time()
@@ -155,7 +187,7 @@ def main():
                 "per_unit": f"{ops:.3g} ops per frame (v-disparity DP: D x H x 7 taps x add+min)"}
     roof["kernel"] = dom
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     roof["launch_ms"] = kern[dom]["ms_per_launch"]
 
     # single-frame latency (batch of one, synchronous per frame)
