@@ -189,10 +189,19 @@ const char* ld_status_string(ld_status s);
  *   LD_STATE_MX_PATH   int32[height]: DP column c_v (0..2W-1) on road rows, -1 elsewhere
  *   LD_STATE_ENERGY    double[2 * width]
  *   LD_STATE_TRACE     int32[2 * 3 * max_rounds]: per RANSAC round (best hypothesis,
- *                      its inlier count, points in the round), beta then gamma */
+ *                      its inlier count, points in the round), beta then gamma
+ *   LD_STATE_LANE_BITS uint8[4 * 16 * width]: network decisions of the last
+ *                      ld_cnn_forward / ld_detect_pruned, band k at k * 16 * width
+ *   LD_STATE_PRUNE     int32[16] of the last ld_detect_pruned: bands, fallback bits (1 plain
+ *                      V_px search, 2 plain energies, 4 no seed, 8 window edge touched),
+ *                      seed column c_s (-1 none), window lo, hi, pooled marking votes,
+ *                      per-band argmax column [4] (-1 none), per-band votes [4], kept
+ *                      candidates, 0
+ *   LD_STATE_CAND_MASK uint8[2 * width]: candidate mask of the last ld_detect_pruned */
 enum {
     LD_STATE_INFO = 0, LD_STATE_MY_PATH = 1, LD_STATE_BETA = 2, LD_STATE_GAMMA = 3, LD_STATE_TABLES = 4,
-    LD_STATE_ROWCOUNT = 5, LD_STATE_EDGES = 6, LD_STATE_MX_PATH = 7, LD_STATE_ENERGY = 8, LD_STATE_TRACE = 9
+    LD_STATE_ROWCOUNT = 5, LD_STATE_EDGES = 6, LD_STATE_MX_PATH = 7, LD_STATE_ENERGY = 8, LD_STATE_TRACE = 9,
+    LD_STATE_LANE_BITS = 10, LD_STATE_PRUNE = 11, LD_STATE_CAND_MASK = 12
 };
 
 /* A robust polynomial fit: coefficients in the variable s = (v - center) / 2^kshift, and
@@ -219,6 +228,95 @@ ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t 
  * nullable) since profiling was enabled. */
 ld_status ld_frame_profile(ld_frame f, int32_t enable);
 ld_status ld_frame_kernel_times(ld_frame f, double* ms_out, int64_t* calls_out, int32_t n);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned candidate pruning (not part of the paper's method).
+ *
+ * A convolutional network, 3x3 convolutions 4 -> 16 -> 16 -> 1 channels with ReLU after the
+ * first two and zero padding, looks at n_bands bands of 16 road rows per frame (band k, k = 0
+ * at the bottom, starts at row (H-16) - ((R-16) k) / n_bands, R = H - v_h road rows; frames
+ * with fewer than 16 road rows have no band).  Its 4 inputs per pixel are I/255,
+ * sqrt(G_x^2 + G_y^2)/1020, atan2(G_y, G_x)/pi with the Sobel pair of the lane detector, and
+ * the disparity residual clamp((D - f(v))/varpi, -4, 4) (-4 where D is invalid).  Its output
+ * logit z scores "lane marking"; a pixel counts as marking when sigmoid(z) >= theta.  Weights
+ * are FP32 masters with BF16 copies feeding MFMA tiles that accumulate in FP32.
+ *
+ * Parameters, LD_CNN_PARAMS floats in this order: w1[3][3][4][16] (row offset, column
+ * offset, input, output), b1[16], w2[3][3][16][16], b2[16], w3[3][3][16][1], b3[1].
+ *
+ * Training (ld_cnn_train_step) runs the forward pass, the loss
+ *   L = inv_norm * sum over labelled pixels of  pos_weight * y * softplus(-z) + (1 - y) * softplus(z),
+ * the backward pass and, when lr > 0, one Adam step (beta1 0.9, beta2 0.999, eps 1e-8); the
+ * gradient is reduced over the workgroups in a fixed order, so a step is deterministic.
+ * Labels (u8, batch x n_bands x 16 x width): 1 marking, 0 not, 255 ignored.
+ */
+typedef struct ld_cnn_s* ld_cnn;
+
+#define LD_CNN_PARAMS 3057
+
+typedef struct ld_cnn_config {
+    int32_t n_bands;      /* bands of 16 rows per frame, 1..4 (default 2) */
+    float theta;          /* marking probability threshold, (0, 1) (0.5) */
+    int32_t delta_x;      /* half width of the V_px search window around the seed, 1..127 (112) */
+    int32_t dilate;       /* candidates kept on each side of a candidate whose track hits
+                             marking, 0..64; -1 (default) keeps every candidate */
+    int32_t min_votes;    /* fewest marking votes that make a seed (8) */
+    int32_t max_batch;    /* frames per training step (sizes the gradient scratch) (32) */
+    int32_t max_width;    /* widest frame trained on (1920) */
+    int32_t seed_ransac;  /* 1: hypothesis 0 of the V_px RANSAC is the line through the band
+                             estimates; 0 (default): RANSAC as in the plain search */
+} ld_cnn_config;
+
+void ld_cnn_config_default(ld_cnn_config* c);
+/* params: host, LD_CNN_PARAMS floats, nullable (all zero).  Runs on the current device. */
+ld_status ld_cnn_create(const ld_cnn_config* c, const float* params, ld_cnn* out);
+ld_status ld_cnn_destroy(ld_cnn n);
+/* Host copies of the FP32 master weights; set also clears the optimiser state. Synchronous. */
+ld_status ld_cnn_set_params(ld_cnn n, const float* params);
+ld_status ld_cnn_get_params(ld_cnn n, float* params);
+
+/* Network decisions for the active frames of f into f's band buffer (needs ld_vdisp on f;
+ * LD_E_STATE otherwise).  prob_out: nullable device float batch x n_bands x 16 x width,
+ * sigmoid(z) (0 where a frame has no band).  The frame format must have varpi > 0. */
+ld_status ld_cnn_forward(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                         int64_t disp_pitch, float* prob_out, void* hip_stream);
+
+/* Training labels from a finished plain detection of f (ld_detect / ld_peaks with curves):
+ * 1 where a band pixel of row v lies within radius + radius_per_disp * f(v) columns of a
+ * detected lane curve (f: the road disparity of the row, so that the label covers the marking
+ * at every distance), else 0; 255 on frames without bands.  lanes: device batch entries;
+ * curves: device batch x 16 x height. */
+ld_status ld_cnn_labels(ld_cnn n, ld_frame f, const ld_lanes* lanes, const float* curves, float radius,
+                        float radius_per_disp, uint8_t* labels_out, void* hip_stream);
+
+/* One training step over the active frames of f (needs ld_vdisp on f).  loss_out (nullable,
+ * device float) and grad_out (nullable, device LD_CNN_PARAMS floats) receive the loss and
+ * gradient at the weights before the update.  LD_E_INVAL if active frames x n_bands x
+ * ceil(width / 60) exceeds max_batch x n_bands x ceil(max_width / 60). */
+ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                            int64_t disp_pitch, const uint8_t* labels, float pos_weight, float inv_norm, float lr,
+                            float* loss_out, float* grad_out, void* hip_stream);
+
+/* The whole path with the network narrowing the search, for the active frames of f:
+ *  1. ld_vdisp, the network's band decisions, edges and votes as in ld_detect;
+ *  2. seed: the votes of marking edges in the bands, histogrammed per band; the pooled
+ *     histogram's argmax c_s (ties to the smaller column) centres the window
+ *     [c_s - delta_x, c_s + delta_x] of V_px columns; with seed_ransac, RANSAC hypothesis 0
+ *     is the line through the argmax columns (at the ninth row of each band) of the lowest
+ *     and the highest band with at least min_votes votes (a constant with one such band);
+ *  3. the band accumulator and row DP inside that window, then RANSAC of the V_px fit;
+ *  4. candidate mask: candidate i is kept if its track, evaluated on the band rows as
+ *     u_v = fma(a_v, u_start, b_v) with a_{v_max} = 1, b_{v_max} = 0,
+ *     a_v = B_v a_{v+1}, b_v = fma(B_v, b_{v+1}, A_v), column floor(u_v + 0.5), meets a
+ *     marking pixel; kept candidates are dilated by `dilate`;
+ *  5. energies of the kept candidates (0 for the others) and peaks.
+ * Fallback to the plain search (LD_FLAG_FALLBACK) for a frame: no seed (fewer than
+ * min_votes marking votes), or the window path touches an inner window edge -> plain
+ * accumulator, DP and unseeded RANSAC; no lane, or a lane next to a pruned candidate ->
+ * energies of every candidate and peaks again. */
+ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                           int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
+                           ld_lanes* lanes_out, float* curves_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of frames from many camera streams.

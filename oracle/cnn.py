@@ -143,3 +143,51 @@ def adam_step(p, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[k] / (1 - b2 ** t)
         out[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
     return out
+
+
+# ----------------------------------------------------------------------------- glue
+ORDER = [("w1", (3, 3, C_IN, C_HID)), ("b1", (C_HID,)), ("w2", (3, 3, C_HID, C_HID)), ("b2", (C_HID,)),
+         ("w3", (3, 3, C_HID, 1)), ("b3", (1,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in ORDER)
+
+
+def flat(p):
+    """Parameters as one vector in the library's order: w1, b1, w2, b2, w3, b3 (row-major)."""
+    return np.concatenate([np.asarray(p[k], np.float64).reshape(-1) for k, _ in ORDER])
+
+
+def unflat(v):
+    out, o = {}, 0
+    for k, s in ORDER:
+        n = int(np.prod(s))
+        out[k] = np.asarray(v[o:o + n], np.float64).reshape(s)
+        o += n
+    return out
+
+
+def disparity_values(disp):
+    """D and validity per pixel: u8 raw (0 invalid), f32 raw (finite and > 0), u16 raw / 16 (0 invalid)."""
+    if disp.dtype == np.uint8:
+        return disp.astype(np.float64), disp != 0
+    if disp.dtype == np.float32:
+        ok = np.isfinite(disp) & (disp > 0)
+        return np.where(ok, disp, 0).astype(np.float64), ok
+    return disp.astype(np.float64) / 16.0, disp != 0
+
+
+def band_top(v_h, H, n_bands, k):
+    """First row of band k (0 = bottom) of 16 road rows, or -1 when the road has fewer than 16 rows."""
+    R = H - v_h
+    if R < 16 or n_bands < 1:
+        return -1
+    return (H - 16) - ((R - 16) * k) // n_bands
+
+
+def band_features(grey, disp, f_table, top, varpi=3.0):
+    """The network input of the 16-row band starting at `top` of a frame: [16, W, 4]."""
+    H, W = grey.shape
+    g = np.zeros((18, W), np.float64)
+    lo, hi = max(top - 1, 0), min(top + 17, H)
+    g[lo - (top - 1):hi - (top - 1)] = grey[lo:hi]
+    D, ok = disparity_values(disp[top:top + 16])
+    return features(g, D, ok, np.asarray(f_table)[top:top + 16], varpi)

@@ -715,9 +715,42 @@ struct ldref_out {
     int32_t* trace_gamma;  // 3 x max_rounds
 };
 
+// Inputs and outputs of the narrowed search (learned part; the steps are defined with the
+// library's ld_detect_pruned, not by the paper).
+struct ldref_learned {
+    int32_t n_bands, delta_x, dilate, min_votes, seed_ransac, pad;
+    const uint8_t* lane_bits;   // 4 x 16 x W decisions of the network, band k at k * 16 * W
+    int32_t prune[16];          // out: bands, fallback bits, c_s, lo, hi, votes, est[4], cnt[4], kept, 0
+    uint8_t* cand_mask;         // out, nullable: 2W
+};
+
+static int band_top(int v_h, int H, int nb, int k) {
+    const int R = H - v_h;
+    if (R < 16 || nb < 1) return -1;
+    return (H - 16) - ((R - 16) * k) / nb;
+}
+
+static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
+                       int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
+                       const double* seed_gamma, ldref_out* o, ldref_learned* L);
+
 int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
                  int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
                  const double* seed_gamma, ldref_out* o) {
+    return detect_impl(grey, gpitch, disp, dpitch, W, H, fmt, d_max, P, stream_id, frame_idx, seed_gamma, o, nullptr);
+}
+
+int ldref_detect_pruned(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
+                        int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
+                        ldref_learned* L, ldref_out* o) {
+    return detect_impl(grey, gpitch, disp, dpitch, W, H, fmt, d_max, P, stream_id, frame_idx, nullptr, o, L);
+}
+
+}  // extern "C"
+
+static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
+                       int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
+                       const double* seed_gamma, ldref_out* o, ldref_learned* L) {
     const int D1 = d_max + 1;
     const int W2 = 2 * W, half = W / 2, v_max = H - 1;
     o->flags = 0; o->v_h = H; o->v_end = H; o->n_lanes = 0; o->n_my = 0; o->n_edges = 0; o->n_votes = 0;
@@ -747,7 +780,18 @@ int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t 
     ldref_ransac(px.data(), py.data(), n_my, 2, P->tr_y, P->n_hyp, P->max_rounds, P->eps_num, P->eps_den,
                  P->seed, stream_id, frame_idx, 0, nullptr, &o->beta, o->trace_beta);
     if (o->beta.flags & 1) o->flags |= 4;
-    if (!o->beta.ok) { o->flags |= 1; return 0; }
+    if (L) {
+        for (int i = 0; i < 16; ++i) L->prune[i] = 0;
+        L->prune[0] = L->n_bands;
+        L->prune[1] = 1 | 4;          // no seed until one is found
+        L->prune[2] = -1;
+        L->prune[4] = -1;
+        for (int k = 0; k < 4; ++k) L->prune[6 + k] = -1;
+        L->prune[14] = 2 * W;
+        if (L->cand_mask) for (int i = 0; i < 2 * W; ++i) L->cand_mask[i] = 1;
+    }
+    const int fb_flag = L ? 16 : 0;   // a frame that never reaches the narrowed search falls back
+    if (!o->beta.ok) { o->flags |= 1 | fb_flag; return 0; }
     std::vector<double> f(H), fp(H), vpy(H);
     int32_t v_h = H;
     ldref_road_tables(&o->beta, H, f.data(), fp.data(), vpy.data(), &v_h);
@@ -756,7 +800,7 @@ int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t 
     if (o->fp) std::memcpy(o->fp, fp.data(), sizeof(double) * H);
     if (o->vpy) std::memcpy(o->vpy, vpy.data(), sizeof(double) * H);
     const int R = v_max - v_h + 1;
-    if (R < 8) { o->flags |= 1; return 0; }
+    if (R < 8) { o->flags |= 1 | fb_flag; return 0; }
 
     // S4: gradient, road mask, edges
     const int cap = W * H;
@@ -775,15 +819,100 @@ int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t 
     std::vector<int64_t> mx((size_t)H * W2, 0);
     ldref_band(h.data(), H, W2, v_h, P->chi, mx.data());
     std::vector<int32_t> cpath(H, -1);
-    ldref_row_dp(mx.data(), H, W2, v_h, P->tau_x_max, P->lambda_x, cpath.data());
+    int fb = 0;
+    std::vector<double> seed_line(5, 0.0);
+    if (L) {
+        // seed from the votes of marking edges on the bands
+        const int nb = L->n_bands;
+        std::vector<int> hp(W2, 0), hb(W2);
+        int est[4] = {-1, -1, -1, -1}, cnt[4] = {0, 0, 0, 0};
+        for (int k = 0; k < nb; ++k) {
+            const int top = band_top(v_h, H, nb, k);
+            if (top < 0) break;
+            std::fill(hb.begin(), hb.end(), 0);
+            for (int i = 0; i < ne; ++i) {
+                const int r = ev[i] - top;
+                if (r < 0 || r >= 16 || ebin[i] < 0 || !L->lane_bits[((size_t)k * 16 + r) * W + eu[i]]) continue;
+                hb[ebin[i]] += 1;
+                hp[ebin[i]] += 1;
+            }
+            int tot = 0, best = 0;
+            for (int c = 0; c < W2; ++c) { tot += hb[c]; if (hb[c] > hb[best]) best = c; }
+            est[k] = tot > 0 ? best : -1;
+            cnt[k] = tot;
+        }
+        int tot = 0, cs = 0;
+        for (int c = 0; c < W2; ++c) { tot += hp[c]; if (hp[c] > hp[cs]) cs = c; }
+        int lo = 0, hi = -1;
+        if (tot < L->min_votes) {
+            fb = 1 | 4;
+            cs = -1;
+        } else {
+            lo = std::max(0, cs - L->delta_x);
+            hi = std::min(W2 - 1, cs + L->delta_x);
+            if (hi - lo + 1 > W) fb = 1 | 4;
+        }
+        int klo = -1, khi = -1;
+        for (int k = 0; k < nb; ++k)
+            if (cnt[k] >= L->min_votes) { if (klo < 0) klo = k; khi = k; }
+        if (cs >= 0 && L->seed_ransac) {
+            if (klo >= 0 && khi != klo) {
+                const double v0 = (double)(band_top(v_h, H, nb, klo) + 8), v1 = (double)(band_top(v_h, H, nb, khi) + 8);
+                const double u0 = (double)(est[klo] - half), u1 = (double)(est[khi] - half);
+                const double g1 = (u1 - u0) / (v1 - v0);
+                seed_line[1] = g1;
+                seed_line[0] = u0 - g1 * v0;
+            } else {
+                seed_line[0] = (double)((klo >= 0 ? est[klo] : cs) - half);
+            }
+        }
+        L->prune[2] = cs; L->prune[3] = lo; L->prune[4] = hi; L->prune[5] = tot;
+        for (int k = 0; k < 4; ++k) { L->prune[6 + k] = est[k]; L->prune[10 + k] = cnt[k]; }
+        if (!(fb & 1)) {
+            // the row DP of O10 restricted to columns lo..hi
+            const int win = hi - lo + 1, tau_max = P->tau_x_max;
+            std::vector<int64_t> E(win), En(win);
+            std::vector<int8_t> back((size_t)R * win, 0);
+            for (int c = 0; c < win; ++c) E[c] = mx[(size_t)v_max * W2 + lo + c];
+            for (int v = v_max - 1; v >= v_h; --v) {
+                for (int c = 0; c < win; ++c) {
+                    int64_t best = E[c];
+                    int bt = 0;
+                    for (int a = 1; a <= tau_max; ++a)
+                        for (int sgn = -1; sgn <= 1; sgn += 2) {
+                            const int cc = c + sgn * a;
+                            if (cc < 0 || cc >= win) continue;
+                            const int64_t val = E[cc] + (int64_t)P->lambda_x * a;
+                            if (val < best) { best = val; bt = sgn * a; }
+                        }
+                    En[c] = mx[(size_t)v * W2 + lo + c] + best;
+                    back[(size_t)(v - v_h) * win + c] = (int8_t)bt;
+                }
+                std::swap(E, En);
+            }
+            int c = 0;
+            for (int cc = 1; cc < win; ++cc)
+                if (E[cc] < E[c]) c = cc;
+            for (int v = v_h; v <= v_max; ++v) {
+                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) fb |= 1 | 8;
+                cpath[v] = lo + c;
+                if (v < v_max) c += back[(size_t)(v - v_h) * win + c];
+            }
+        }
+        L->prune[1] = fb;
+    }
+    if (!L || (fb & 1)) ldref_row_dp(mx.data(), H, W2, v_h, P->tau_x_max, P->lambda_x, cpath.data());
     if (o->mx_path) std::memcpy(o->mx_path, cpath.data(), sizeof(int32_t) * H);
     std::vector<int32_t> mxv(R), mxu(R);
     for (int v = v_h; v <= v_max; ++v) { mxv[v - v_h] = v; mxu[v - v_h] = cpath[v] - half; }
 
-    // S8: gamma by RANSAC and V_px(v) = g(v) (Eq. vpx_estimation)
+    // S8: gamma by RANSAC and V_px(v) = g(v) (Eq. vpx_estimation); the narrowed search seeds
+    // hypothesis 0 with the line through the band estimates
+    const double* seed = L ? (((fb & 1) || !L->seed_ransac) ? nullptr : seed_line.data()) : seed_gamma;
     ldref_ransac(mxv.data(), mxu.data(), R, 4, P->tr_x, P->n_hyp, P->max_rounds, P->eps_num, P->eps_den,
-                 P->seed, stream_id, frame_idx, 1, seed_gamma, &o->gamma, o->trace_gamma);
+                 P->seed, stream_id, frame_idx, 1, seed, &o->gamma, o->trace_gamma);
     if (o->gamma.flags & 1) o->flags |= 8;
+    if (L && (fb & 1)) o->flags |= 16;
     if (!o->gamma.ok) { o->flags |= 2; return 0; }
     std::vector<double> vpx(H, nan);
     for (int v = v_h; v <= v_max; ++v) vpx[v] = eval_s(o->gamma.coef, 4, o->gamma.center, o->gamma.kshift, v);
@@ -812,14 +941,75 @@ int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t 
     // S12: candidate energies
     std::vector<double> E(W2, 0.0);
     o->v_end = ldref_energy(m1.data(), vpx.data(), vpy.data(), W, H, v_h, E.data(), nullptr, nullptr, 0);
+    const int dn = P->d_nms > 0 ? P->d_nms : std::max(8, W / 64);
+    if (L && !(fb & 1) && L->dilate >= 0) {
+        // candidate mask: tracks through the band rows, u_v = fma(a_v, u_start, b_v)
+        const int nb = L->n_bands;
+        std::vector<double> Av(H, 0.0), Bv(H, 0.0);
+        for (int v = v_max - 1; v >= o->v_end; --v) {
+            const double den = (double)(v + 1) - vpy[v + 1];
+            Av[v] = vpx[v + 1] / den;
+            Bv[v] = ((double)v - vpy[v + 1]) / den;
+        }
+        const int top_hi = band_top(v_h, H, nb, nb - 1);
+        std::vector<double> ta((size_t)nb * 16, 0.0), tb((size_t)nb * 16, 0.0);
+        double a = 1.0, c = 0.0;
+        for (int v = v_max; v >= top_hi; --v) {
+            if (v < v_max) { a = Bv[v] * a; c = std::fma(Bv[v], c, Av[v]); }
+            for (int k = 0; k < nb; ++k) {
+                const int r = v - band_top(v_h, H, nb, k);
+                if (r >= 0 && r < 16) { ta[(size_t)k * 16 + r] = a; tb[(size_t)k * 16 + r] = c; }
+            }
+        }
+        std::vector<uint8_t> hit(W2, 0), keep(W2, 0);
+        for (int i = 0; i < W2; ++i) {
+            const double us = (double)(i - half);
+            for (int k = 0; k < nb && !hit[i]; ++k) {
+                const int top = band_top(v_h, H, nb, k);
+                for (int r = 0; r < 16; ++r) {
+                    if (top + r < o->v_end) continue;
+                    const double x = std::fma(ta[(size_t)k * 16 + r], us, tb[(size_t)k * 16 + r]) + 0.5;
+                    if (x >= 0.0 && x < (double)W) {
+                        const int col = (int)std::floor(x);
+                        if (L->lane_bits[((size_t)k * 16 + r) * W + col]) { hit[i] = 1; break; }
+                    }
+                }
+            }
+        }
+        int kept = 0;
+        for (int i = 0; i < W2; ++i) {
+            for (int j = std::max(0, i - L->dilate); j <= std::min(W2 - 1, i + L->dilate); ++j) keep[i] |= hit[j];
+            kept += keep[i];
+        }
+        L->prune[14] = kept;
+        if (L->cand_mask) std::memcpy(L->cand_mask, keep.data(), W2);
+        std::vector<double> Em(W2);
+        for (int i = 0; i < W2; ++i) Em[i] = keep[i] ? E[i] : 0.0;
+        int32_t us[16];
+        double el[16];
+        const int n = ldref_peaks(Em.data(), W2, half, P->rho_lpv, dn, us, el);
+        bool bad = n == 0;
+        for (int l = 0; l < n; ++l) {
+            const int i = us[l] + half;
+            bad = bad || !keep[i - 1] || !keep[i + 1];
+        }
+        if (bad) {
+            fb |= 2;
+            L->prune[1] = fb;
+            o->flags |= 16;
+        } else {
+            E = Em;
+        }
+    }
     if (o->energy) std::memcpy(o->energy, E.data(), sizeof(double) * W2);
 
     // S13: peaks and lane curves
-    const int dn = P->d_nms > 0 ? P->d_nms : std::max(8, W / 64);
     o->n_lanes = ldref_peaks(E.data(), W2, half, P->rho_lpv, dn, o->u_start, o->energy_lane);
     if (o->curves && o->n_lanes > 0)
         ldref_energy(m1.data(), vpx.data(), vpy.data(), W, H, v_h, nullptr, o->curves, o->u_start, o->n_lanes);
     return 0;
 }
+
+extern "C" {
 
 }  // extern "C"

@@ -96,6 +96,9 @@ def lib():
         L.ldref_peaks.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_int, _P32, _PD]
         L.ldref_detect.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.POINTER(Params), C.c_uint64, C.c_int64, _PD, C.POINTER(Out)]
+        L.ldref_detect_pruned.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                          C.c_int, C.POINTER(Params), C.c_uint64, C.c_int64, C.POINTER(Learned),
+                                          C.POINTER(Out)]
         _lib = L
     return _lib
 
@@ -283,8 +286,32 @@ class Result:
     """Plain container for everything ldref_detect reports about one frame."""
 
 
+class Learned(C.Structure):
+    _fields_ = [("n_bands", C.c_int32), ("delta_x", C.c_int32), ("dilate", C.c_int32), ("min_votes", C.c_int32),
+                ("seed_ransac", C.c_int32), ("pad", C.c_int32),
+                ("lane_bits", C.c_void_p), ("prune", C.c_int32 * 16), ("cand_mask", C.c_void_p)]
+
+
+def detect_pruned(grey: np.ndarray, disp: np.ndarray, d_max: int, lane_bits: np.ndarray, *, n_bands=2, delta_x=112,
+                  dilate=-1, min_votes=8, seed_ransac=0, params: Params | None = None, stream_id=0, frame_idx=0,
+                  want_m1=False):
+    """The narrowed search given the network's band decisions lane_bits (4 x 16 x W u8):
+    everything detect() reports plus .prune (16 int32) and .cand_mask (2W u8)."""
+    H, W = np.asarray(grey).shape
+    bits = np.ascontiguousarray(lane_bits, dtype=np.uint8).reshape(4, 16, W)
+    L = Learned()
+    L.n_bands, L.delta_x, L.dilate, L.min_votes, L.seed_ransac = n_bands, delta_x, dilate, min_votes, seed_ransac
+    L.lane_bits = bits.ctypes.data
+    mask = np.zeros(2 * W, np.uint8)
+    L.cand_mask = mask.ctypes.data
+    r = detect(grey, disp, d_max, params, stream_id=stream_id, frame_idx=frame_idx, want_m1=want_m1, _learned=L)
+    r.prune = np.array(L.prune[:], np.int32)
+    r.cand_mask = mask
+    return r
+
+
 def detect(grey: np.ndarray, disp: np.ndarray, d_max: int, params: Params | None = None, *, stream_id=0,
-           frame_idx=0, seed_gamma=None, want_m1=False, edge_cap=None):
+           frame_idx=0, seed_gamma=None, want_m1=False, edge_cap=None, _learned=None):
     grey = np.ascontiguousarray(grey, dtype=np.uint8)
     disp = np.ascontiguousarray(disp)
     H, W = grey.shape
@@ -326,8 +353,12 @@ def detect(grey: np.ndarray, disp: np.ndarray, d_max: int, params: Params | None
     if seed_gamma is not None:
         sg = np.ascontiguousarray(seed_gamma, dtype=np.float64)
     fmt = _fmt_of(disp)
-    lib().ldref_detect(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H, fmt, d_max,
-                       C.byref(params), stream_id, frame_idx, _pd(sg) if sg is not None else None, C.byref(o))
+    if _learned is None:
+        lib().ldref_detect(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H, fmt, d_max,
+                           C.byref(params), stream_id, frame_idx, _pd(sg) if sg is not None else None, C.byref(o))
+    else:
+        lib().ldref_detect_pruned(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H, fmt,
+                                  d_max, C.byref(params), stream_id, frame_idx, C.byref(_learned), C.byref(o))
     r.flags, r.v_h, r.v_end, r.n_lanes = o.flags, o.v_h, o.v_end, o.n_lanes
     r.n_my, r.n_edges, r.n_votes = o.n_my, o.n_edges, o.n_votes
     r.my_x = r.my_x[: o.n_my]

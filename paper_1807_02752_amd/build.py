@@ -24,7 +24,8 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp,
-           os.path.join(CSRC, "ld.hip"), os.path.join(CSRC, "ld_server.hip")]
+           os.path.join(CSRC, "ld.hip"), os.path.join(CSRC, "ld_server.hip"),
+           os.path.join(CSRC, "ld_cnn.hip")]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

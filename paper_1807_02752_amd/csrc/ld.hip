@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "ld_device.h"
+#include "ld_internal.h"
 
 using namespace ldk;
 
@@ -59,10 +60,25 @@ struct Dev {
     int32_t* trace;     // B x 2 x 3 x kMaxRounds
     float* qbuf;        // B x H x W    G_x w_g of every road edge, in bucket order
     uint32_t* rbound;   // B x H x 2    raw disparity interval of the road test per row
+    uint8_t* lbits;     // B x 4 x 16 x W   network decisions on the bands (pruned search)
+    int32_t* prune;     // B x 16       pruned-search state (LD_STATE_PRUNE layout)
+    uint8_t* cmask;     // B x 2W       candidate mask of the pruned search
+    double* seedg;      // B x 5        RANSAC hypothesis 0 of the pruned search (raw basis)
     const int32_t* nact;   // nullable device count: frames b >= *nact of a launch are skipped
+    // nullable: run only the frames whose fallback bits prune[b][1] & only_bits are
+    // non-zero (only_set = 1) or zero (only_set = 0)
+    const int32_t* only;
+    int only_bits, only_set;
 };
 
-__device__ __forceinline__ bool frame_masked(const Dev& d, int b) { return d.nact != nullptr && b >= *d.nact; }
+constexpr int kPruneWords = 16;
+constexpr int kFbPlainVpx = 1, kFbPlainEnergy = 2, kFbNoSeed = 4, kFbTouch = 8;
+
+__device__ __forceinline__ bool frame_masked(const Dev& d, int b) {
+    if (d.nact != nullptr && b >= *d.nact) return true;
+    if (d.only != nullptr && (((d.only[b * kPruneWords + 1] & d.only_bits) != 0) != (d.only_set != 0))) return true;
+    return false;
+}
 
 // ------------------------------------------------------------------------------------------
 // Block-wide helpers (any multiple of 64 threads up to 1024)
@@ -780,6 +796,63 @@ __host__ __device__ __forceinline__ int vpx_walk_words_dev(int W2) {
 
 __device__ __forceinline__ int rank_to_tau(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
 
+// S8 tail shared by the full and the windowed V_px search: RANSAC of the quartic through the
+// path points (PX = rows, PY = u columns), V_px and the track tables, frame info.
+__device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int* cur, int* cur2, uint32_t* bitmap,
+                             int bm_words, RansacShared& S, const uint64_t* stream_ids, const int64_t* frame_idx,
+                             const double* seed, double* vp_out, int ne, int nv) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int H = d.H, v_max = H - 1, v_h = fi.v_h, R = v_max - v_h + 1;
+    double* tf = d.tab + (int64_t)b * 6 * H;
+    double* tvpy = tf + 2 * H;
+    double* tvpx = tf + 3 * H;
+    double* tA = tf + 4 * H;
+    double* tB = tf + 5 * H;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    const uint64_t sid = stream_ids ? stream_ids[b] : 0ull;
+    const uint64_t fid = frame_idx ? (uint64_t)frame_idx[b] : (uint64_t)b;
+    FitRes* fit = d.fit + 2 * b + 1;
+    ransac_block<4>(PX, PY, R, cur, cur2, bitmap, bm_words, S, d.P.tr_x, d.P, sid, fid, 1,
+                    seed, fit,
+                    d.trace + (int64_t)b * 6 * kMaxRounds + 3 * kMaxRounds);
+    const FitRes& g = *fit;
+    int bad = v_h - 1;
+    if (g.ok) {
+        for (int v = t; v < H; v += nt)
+            tvpx[v] = (v >= v_h) ? eval_s<4>(g.coef, g.center, g.kshift, v) : nan;
+    }
+    __syncthreads();
+    if (g.ok) {
+        for (int v = v_h + t; v <= v_max - 1; v += nt) {
+            const double den = (double)(v + 1) - tvpy[v + 1];
+            if (!(den > 0.0)) {
+                bad = max(bad, v);
+            } else {
+                tA[v] = tvpx[v + 1] / den;
+                tB[v] = ((double)v - tvpy[v + 1]) / den;
+            }
+        }
+    }
+    bad = block_max_i32(bad, S.red);
+    nv = block_sum_i32(nv, S.red);
+    if (t == 0) {
+        fi.flags |= (g.flags & 1) ? LD_FLAG_NOCONS_X : 0;
+        if (!g.ok) fi.flags |= LD_FLAG_NOVP;
+        fi.v_end = g.ok ? bad + 1 : H;
+        fi.n_edges = ne;
+        fi.n_votes = nv;
+        fi.n_mx = R;
+        d.info[b] = fi;
+    }
+    if (vp_out) {
+        for (int v = t; v < H; v += nt) {
+            const bool road = v >= v_h && g.ok;
+            vp_out[((int64_t)b * H + v) * 2] = road ? tvpx[v] : nan;
+            vp_out[((int64_t)b * H + v) * 2 + 1] = v >= v_h ? tvpy[v] : nan;
+        }
+    }
+}
+
 template <int MAXT>
 __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
                                                   const double* seed_gamma, double* vp_out) {
@@ -966,48 +1039,8 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
         }
         __syncthreads();
     }
-    const uint64_t sid = stream_ids ? stream_ids[b] : 0ull;
-    const uint64_t fid = frame_idx ? (uint64_t)frame_idx[b] : (uint64_t)b;
-    FitRes* fit = d.fit + 2 * b + 1;
-    ransac_block<4>(PX, PY, R, cur, cur2, bitmap, bm_words, S, d.P.tr_x, d.P, sid, fid, 1,
-                    seed_gamma ? seed_gamma + 5 * (int64_t)b : nullptr, fit,
-                    d.trace + (int64_t)b * 6 * kMaxRounds + 3 * kMaxRounds);
-    const FitRes& g = *fit;
-    int bad = v_h - 1;
-    if (g.ok) {
-        for (int v = t; v < H; v += nt)
-            tvpx[v] = (v >= v_h) ? eval_s<4>(g.coef, g.center, g.kshift, v) : nan;
-    }
-    __syncthreads();
-    if (g.ok) {
-        for (int v = v_h + t; v <= v_max - 1; v += nt) {
-            const double den = (double)(v + 1) - tvpy[v + 1];
-            if (!(den > 0.0)) {
-                bad = max(bad, v);
-            } else {
-                tA[v] = tvpx[v + 1] / den;
-                tB[v] = ((double)v - tvpy[v + 1]) / den;
-            }
-        }
-    }
-    bad = block_max_i32(bad, S.red);
-    nv = block_sum_i32(nv, S.red);
-    if (t == 0) {
-        fi.flags |= (g.flags & 1) ? LD_FLAG_NOCONS_X : 0;
-        if (!g.ok) fi.flags |= LD_FLAG_NOVP;
-        fi.v_end = g.ok ? bad + 1 : H;
-        fi.n_edges = ne;
-        fi.n_votes = nv;
-        fi.n_mx = R;
-        d.info[b] = fi;
-    }
-    if (vp_out) {
-        for (int v = t; v < H; v += nt) {
-            const bool road = v >= v_h && g.ok;
-            vp_out[((int64_t)b * H + v) * 2] = road ? tvpx[v] : nan;
-            vp_out[((int64_t)b * H + v) * 2 + 1] = v >= v_h ? tvpy[v] : nan;
-        }
-    }
+    vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx,
+                 seed_gamma ? seed_gamma + 5 * (int64_t)b : nullptr, vp_out, ne, nv);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1248,11 +1281,312 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Dev d, ld_lanes* lanes_out, fl
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Pruned search (learned part, not in the paper).  The network's decisions on a few bands of
+// road rows (lbits) select the edges that lie on lane markings; their V_px vote columns give a
+// seed for the V_px path, the DP then runs inside a window around the seed, and the tracks of
+// the candidates through the bands decide which candidates are scored.  Any sign that the
+// narrowed search may differ from the full one sends the frame back to the full search.
+__device__ __forceinline__ int band_top(const Dev& d, int v_h, int nb, int k) { return ldi_band_top(v_h, d.H, nb, k); }
+
+// Seed: per-band histograms of the vote columns of marking edges; pooled argmax c_s; window;
+// RANSAC hypothesis 0 (line through the lowest and the highest band estimates).  One workgroup
+// per frame; LDS 2 x 2W ints.
+__global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int min_votes, int seed_ransac) {
+    extern __shared__ int hs[];
+    __shared__ int64_t rv[kMaxWaves];
+    __shared__ int ri[kMaxWaves];
+    __shared__ int red[kMaxWaves];
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (frame_masked(d, b)) return;
+    const int W = d.W, W2 = d.W2, H = d.H;
+    const FrameInfo fi = d.info[b];
+    int32_t* pr = d.prune + (int64_t)b * kPruneWords;
+    double* sg = d.seedg + (int64_t)b * 5;
+    int* hb = hs;          // band histogram
+    int* hp = hs + W2;     // pooled histogram
+    for (int i = t; i < 2 * W2; i += kBlock) hs[i] = 0;
+    int est[LDI_MAX_BANDS], cnt[LDI_MAX_BANDS];
+    for (int k = 0; k < LDI_MAX_BANDS; ++k) { est[k] = -1; cnt[k] = 0; }
+    const bool road = !(fi.flags & LD_FLAG_NOROAD);
+    const ld_edge* fe = d.edges + (int64_t)b * H * W;
+    const uint8_t* lb = d.lbits + (int64_t)b * LDI_MAX_BANDS * LDI_BAND_ROWS * W;
+    __syncthreads();
+    for (int k = 0; k < nb && road; ++k) {
+        const int top = band_top(d, fi.v_h, nb, k);
+        if (top < 0) break;
+        for (int r = 0; r < LDI_BAND_ROWS; ++r) {
+            const int v = top + r, n = d.rowcnt[(int64_t)b * H + v];
+            for (int i = t; i < n; i += kBlock) {
+                const ld_edge e = fe[(int64_t)v * W + i];
+                if (e.bin >= 0 && lb[(k * LDI_BAND_ROWS + r) * W + e.u]) {
+                    atomicAdd(&hb[e.bin], 1);
+                    atomicAdd(&hp[e.bin], 1);
+                }
+            }
+        }
+        __syncthreads();
+        int64_t key = INT64_MAX;
+        int bi = 0x7fffffff, tot = 0;
+        for (int c = t; c < W2; c += kBlock) {
+            const int h = hb[c];
+            tot += h;
+            if (h > 0 && -(int64_t)h < key) { key = -(int64_t)h; bi = c; }
+            hb[c] = 0;
+        }
+        tot = block_sum_i32(tot, red);
+        block_argmin_i64(key, bi, rv, ri);
+        est[k] = tot > 0 ? bi : -1;
+        cnt[k] = tot;
+    }
+    int64_t key = INT64_MAX;
+    int bi = 0x7fffffff, tot = 0;
+    for (int c = t; c < W2; c += kBlock) {
+        const int h = hp[c];
+        tot += h;
+        if (h > 0 && -(int64_t)h < key) { key = -(int64_t)h; bi = c; }
+    }
+    tot = block_sum_i32(tot, red);
+    block_argmin_i64(key, bi, rv, ri);
+    if (t == 0) {
+        int fb = 0, cs = -1, lo = 0, hi = -1;
+        if (!road || tot < min_votes) {
+            fb = kFbPlainVpx | kFbNoSeed;
+        } else {
+            cs = bi;
+            lo = max(0, cs - delta);
+            hi = min(W2 - 1, cs + delta);
+            if (hi - lo + 1 > W) fb = kFbPlainVpx | kFbNoSeed;   // the window buffer holds W columns per row
+        }
+        // hypothesis 0: line through the lowest and the highest band with min_votes votes
+        int klo = -1, khi = -1;
+        for (int k = 0; k < nb; ++k)
+            if (cnt[k] >= min_votes) { if (klo < 0) klo = k; khi = k; }
+        for (int p = 0; p < 5; ++p) sg[p] = 0.0;
+        if (cs >= 0 && seed_ransac) {
+            if (klo >= 0 && khi != klo) {
+                const double v0 = (double)(band_top(d, fi.v_h, nb, klo) + 8), v1 = (double)(band_top(d, fi.v_h, nb, khi) + 8);
+                const double u0 = (double)(est[klo] - d.half), u1 = (double)(est[khi] - d.half);
+                const double g1 = (u1 - u0) / (v1 - v0);
+                sg[1] = g1;
+                sg[0] = u0 - g1 * v0;
+            } else {
+                sg[0] = (double)((klo >= 0 ? est[klo] : cs) - d.half);
+            }
+        } else {
+            sg[0] = __longlong_as_double(0x7ff8000000000000LL);   // no seed
+        }
+        pr[0] = nb; pr[1] = fb; pr[2] = cs; pr[3] = lo; pr[4] = hi; pr[5] = tot;
+        for (int k = 0; k < 4; ++k) { pr[6 + k] = est[k]; pr[10 + k] = cnt[k]; }
+        pr[14] = 0; pr[15] = 0;
+    }
+}
+
+// Windowed V_px search: band accumulator and row DP on columns lo..hi only (transitions
+// leaving the window are not allowed), the same tie order as the full DP, backtrace, a check
+// that the path never reaches an inner edge of the window, then the fit.  One workgroup of
+// 256 threads per frame (one window column each); the backtrace (int8 per row and window
+// column) uses the frame's backtrace buffer.
+__global__ __launch_bounds__(256) void k_vpx_window(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                    double* vp_out) {
+    extern __shared__ unsigned char smem[];
+    __shared__ RansacShared S;
+    __shared__ int64_t rv[kMaxWaves];
+    __shared__ int ri[kMaxWaves];
+    __shared__ int s_touch;
+    const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    if (frame_masked(d, b)) return;
+    int32_t* pr = d.prune + (int64_t)b * kPruneWords;
+    if (pr[1] & kFbPlainVpx) return;
+    const int H = d.H, W2 = d.W2, v_max = H - 1;
+    FrameInfo fi = d.info[b];
+    double* tf = d.tab + (int64_t)b * 6 * H;
+    for (int v = t; v < H; v += nt) {
+        tf[4 * H + v] = 0.0;
+        tf[5 * H + v] = 0.0;
+        d.mxpath[(int64_t)b * H + v] = -1;
+    }
+    const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
+    const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
+    int* hist = reinterpret_cast<int*>(smem);   // 256
+    int* Ea = hist + 256;
+    int* Eb = Ea + 256;
+    int* PX = Eb + 256;
+    int* PY = PX + H;
+    int* cur = PY + H;
+    int* cur2 = cur + H;
+    int* cntL = cur2 + H;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cntL + H);
+    const int bm_words = (H + 31) / 32;
+    const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
+    for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
+    for (int i = t; i < 256; i += nt) hist[i] = 0;
+    __syncthreads();
+    int ne = 0;
+    for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
+    ne = block_sum_i32(ne, S.red);
+    int nv = 0;
+    auto apply = [&](int r, int sign, bool count) {
+        const int n = cntL[r];
+        for (int i = t; i < n; i += nt) {
+            const int c = fe[(int64_t)r * d.W + i].bin;
+            if (count && c >= 0) ++nv;
+            if (c >= lo && c <= hi) atomicAdd(&hist[c - lo], sign);
+        }
+    };
+    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1, true);
+    __syncthreads();
+    if (t < win) Ea[t] = -hist[t];
+    __syncthreads();
+    const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
+    int8_t* back = reinterpret_cast<int8_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 4;
+    int* E = Ea;
+    int* En = Eb;
+    for (int v = v_max - 1; v >= v_h; --v) {
+        if (v - chi >= v_h) apply(v - chi, 1, true);
+        if (v + chi + 1 <= v_max) apply(v + chi + 1, -1, false);
+        __syncthreads();
+        if (t < win) {
+            int best = E[t], bt = 0;
+            for (int a = 1; a <= tau_max; ++a) {
+                const int cl = t - a, cr = t + a;
+                if (cl >= 0 && E[cl] + lam * a < best) { best = E[cl] + lam * a; bt = -a; }
+                if (cr < win && E[cr] + lam * a < best) { best = E[cr] + lam * a; bt = a; }
+            }
+            En[t] = -hist[t] + best;
+            back[(int64_t)(v - v_h) * win + t] = (int8_t)bt;
+        }
+        __syncthreads();
+        int* tmp = E; E = En; En = tmp;
+    }
+    int64_t bv = INT64_MAX;
+    int bc = 0x7fffffff;
+    if (t < win) { bv = E[t]; bc = t; }
+    block_argmin_i64(bv, bc, rv, ri);
+    if (t == 0) {
+        int c = bc, touch = 0;
+        for (int v = v_h; v <= v_max; ++v) {
+            if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
+            d.mxpath[(int64_t)b * H + v] = lo + c;
+            PX[v - v_h] = v;
+            PY[v - v_h] = lo + c - d.half;
+            if (v < v_max) c += back[(int64_t)(v - v_h) * win + c];
+        }
+        s_touch = touch;
+        if (touch) pr[1] |= kFbPlainVpx | kFbTouch;
+    }
+    __syncthreads();
+    if (s_touch) return;
+    vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx, d.seedg + (int64_t)b * 5,
+                 vp_out, ne, nv);
+}
+
+// Candidate mask: candidate i is kept when its track meets a marking pixel on a band row, then
+// dilated.  Frames on the plain V_px search keep every candidate.  One workgroup per frame.
+__global__ __launch_bounds__(kBlock) void k_cand_mask(Dev d, int nb, int dilate) {
+    extern __shared__ unsigned char smem[];
+    __shared__ double ta[LDI_MAX_BANDS * LDI_BAND_ROWS], tb[LDI_MAX_BANDS * LDI_BAND_ROWS];
+    __shared__ int red[kMaxWaves];
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (frame_masked(d, b)) return;
+    const int W = d.W, W2 = d.W2, H = d.H, v_max = H - 1;
+    int32_t* pr = d.prune + (int64_t)b * kPruneWords;
+    uint8_t* cm = d.cmask + (int64_t)b * W2;
+    const FrameInfo fi = d.info[b];
+    if ((pr[1] & kFbPlainVpx) || (fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP)) || dilate < 0) {
+        for (int i = t; i < W2; i += kBlock) cm[i] = 1;
+        if (t == 0) pr[14] = W2;
+        return;
+    }
+    const int wpr = (W + 31) / 32;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(smem);            // nb x 16 x wpr
+    uint8_t* hit = reinterpret_cast<uint8_t*>(bits + nb * LDI_BAND_ROWS * wpr);   // W2
+    const uint8_t* lb = d.lbits + (int64_t)b * LDI_MAX_BANDS * LDI_BAND_ROWS * W;
+    for (int w = t; w < nb * LDI_BAND_ROWS * wpr; w += kBlock) {
+        const int row = w / wpr, c0 = (w % wpr) * 32;
+        uint32_t x = 0;
+        for (int j = 0; j < 32 && c0 + j < W; ++j) x |= (lb[row * W + c0 + j] ? 1u : 0u) << j;
+        bits[w] = x;
+    }
+    const double* tA = d.tab + (int64_t)b * 6 * H + 4 * H;
+    const double* tB = tA + H;
+    const int v_end = fi.v_end;
+    const int top_hi = band_top(d, fi.v_h, nb, nb - 1);
+    if (t == 0) {
+        double a = 1.0, c = 0.0;
+        for (int v = v_max; v >= top_hi; --v) {
+            if (v < v_max) {
+                a = tB[v] * a;
+                c = fma(tB[v], c, tA[v]);
+            }
+            for (int k = 0; k < nb; ++k) {
+                const int r = v - band_top(d, fi.v_h, nb, k);
+                if (r >= 0 && r < LDI_BAND_ROWS) { ta[k * LDI_BAND_ROWS + r] = a; tb[k * LDI_BAND_ROWS + r] = c; }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < W2; i += kBlock) {
+        const double us = (double)(i - d.half);
+        uint8_t h = 0;
+        for (int k = 0; k < nb && !h; ++k) {
+            const int top = band_top(d, fi.v_h, nb, k);
+            for (int r = 0; r < LDI_BAND_ROWS; ++r) {
+                if (top + r < v_end) continue;
+                const double x = fma(ta[k * LDI_BAND_ROWS + r], us, tb[k * LDI_BAND_ROWS + r]) + 0.5;
+                if (x >= 0.0 && x < (double)W) {
+                    const int col = (int)floor(x);
+                    if ((bits[(k * LDI_BAND_ROWS + r) * wpr + (col >> 5)] >> (col & 31)) & 1u) { h = 1; break; }
+                }
+            }
+        }
+        hit[i] = h;
+    }
+    __syncthreads();
+    int kept = 0;
+    for (int i = t; i < W2; i += kBlock) {
+        uint8_t k = 0;
+        for (int j = max(0, i - dilate); j <= min(W2 - 1, i + dilate); ++j) k |= hit[j];
+        cm[i] = k;
+        kept += k;
+    }
+    kept = block_sum_i32(kept, red);
+    if (t == 0) pr[14] = kept;
+}
+
+// After the masked energies and peaks: a frame on the narrowed search falls back to the full
+// energies when it found no lane or a lane sits next to a pruned candidate.  Marks
+// LD_FLAG_FALLBACK on every frame that used any part of the full search.
+__global__ void k_lane_check(Dev d, ld_lanes* lanes, int nframes, int pruning) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nframes || frame_masked(d, b)) return;
+    int32_t* pr = d.prune + (int64_t)b * kPruneWords;
+    const uint8_t* cm = d.cmask + (int64_t)b * d.W2;
+    int fb = pr[1];
+    const FrameInfo fi = d.info[b];
+    if (pruning && !(fb & kFbPlainVpx) && !(fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP))) {
+        const int n = lanes[b].n;
+        bool bad = n == 0;
+        for (int l = 0; l < n; ++l) {
+            const int i = lanes[b].u_start[l] + d.half;
+            bad = bad || cm[i - 1] == 0 || cm[i + 1] == 0;
+        }
+        if (bad) fb |= kFbPlainEnergy;
+    }
+    pr[1] = fb;
+    if (fb & (kFbPlainVpx | kFbPlainEnergy)) {
+        d.info[b].flags = fi.flags | LD_FLAG_FALLBACK;
+        lanes[b].flags |= LD_FLAG_FALLBACK;
+    }
+}
+
 }  // namespace
 
 // ==========================================================================================
 // Host side: frame objects and the C ABI.
-constexpr int kNumKernels = 6;   // k_vdisp_hist, k_vdisp_fit, k_edges, k_vpx_fit, k_energy, k_peaks
+// k_vdisp_hist, k_vdisp_fit, k_edges, k_vpx_fit, k_energy, k_peaks, then the pruned search:
+// k_cnn_fwd, k_seed, k_vpx_window, k_cand_mask + k_lane_check
+constexpr int kNumKernels = 10;
 
 struct ProfEvent {
     int kernel;
@@ -1264,8 +1598,8 @@ struct ld_frame_s {
     bool prof = false;                  // bracket every kernel launch with HIP events
     std::vector<ProfEvent> pending;     // recorded, not yet read
     std::vector<ProfEvent> pool;        // reusable event pairs
-    double acc_ms[kNumKernels] = {0, 0, 0, 0, 0, 0};
-    int64_t calls[kNumKernels] = {0, 0, 0, 0, 0, 0};
+    double acc_ms[kNumKernels] = {};
+    int64_t calls[kNumKernels] = {};
     int batch;          // allocated frames
     int active;         // frames processed by the next calls
     void* mem;          // one device allocation holding all scratch
@@ -1273,6 +1607,7 @@ struct ld_frame_s {
     int device;
     hipStream_t last;
     int stage;          // 0 nothing, 1 vdisp done, 2 vp done, 3 energy done
+    int bands;          // bands of the last network decisions (0 none since the last ld_vdisp)
 };
 
 namespace {
@@ -1346,7 +1681,7 @@ void allow_lds(K kernel, size_t bytes) {
     }
 }
 
-constexpr int kRegions = 14;
+constexpr int kRegions = 18;
 
 // Byte offsets and sizes of the regions of one frame object's device allocation.
 size_t frame_layout(int width, int height, int batch, int d_max, size_t* off, size_t* sz) {
@@ -1366,6 +1701,10 @@ size_t frame_layout(int width, int height, int batch, int d_max, size_t* off, si
         B * 6 * kMaxRounds * 4,         // trace
         B * H * W * 4,                  // qbuf
         B * H * 2 * 4,                  // rbound
+        B * LDI_MAX_BANDS * LDI_BAND_ROWS * W,   // lbits
+        B * kPruneWords * 4,            // prune
+        B * W2,                         // cmask
+        B * 5 * 8,                      // seedg
     };
     size_t o = 0;
     for (int i = 0; i < kRegions; ++i) {
@@ -1421,58 +1760,67 @@ ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t*
     return launch_ok();
 }
 
-ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, const uint64_t* sid,
-                 const int64_t* fidx, const double* seed_gamma, double* vp_out, hipStream_t st) {
+ld_status run_edges(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, hipStream_t st) {
     Dev& d = f->d;
     dim3 g3((d.W + 4 * kQT - 1) / (4 * kQT), (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
-    {
-        ProfScope ps(f, 2, st);
-        if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
-        else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
-        else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
-    }
-    if (launch_ok() != LD_OK) return LD_E_HIP;
+    ProfScope ps(f, 2, st);
+    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+    else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+    return launch_ok();
+}
+
+// the full V_px search of S6-S8 for the frames that `d` selects
+ld_status run_vpx(ld_frame f, const Dev& d, const uint64_t* sid, const int64_t* fidx, const double* seed_gamma,
+                  double* vp_out, hipStream_t st) {
     const size_t l4 = vpx_fit_lds(d);
     const int nt4 = vpx_fit_threads(d);
-    {
-        ProfScope ps(f, 3, st);
-        if (nt4 <= 512) {
-            allow_lds(k_vpx_fit<512>, l4);
-            hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
-        } else {
-            allow_lds(k_vpx_fit<1024>, l4);
-            hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
-        }
+    ProfScope ps(f, 3, st);
+    if (nt4 <= 512) {
+        allow_lds(k_vpx_fit<512>, l4);
+        hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
+    } else {
+        allow_lds(k_vpx_fit<1024>, l4);
+        hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
     }
     return launch_ok();
+}
+
+ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, const uint64_t* sid,
+                 const int64_t* fidx, const double* seed_gamma, double* vp_out, hipStream_t st) {
+    ld_status s = run_edges(f, grey, gp, disp, dpt, st);
+    if (s == LD_OK) s = run_vpx(f, f->d, sid, fidx, seed_gamma, vp_out, st);
+    return s;
 }
 
 template <int NC, int NT>
-void launch_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
-    const size_t l = energy_lds(f->d);
+void launch_energy(ld_frame f, const Dev& d, const uint8_t* mask, float* eout, hipStream_t st) {
+    const size_t l = energy_lds(d);
     allow_lds(k_energy<NC, NT>, l);
-    hipLaunchKernelGGL((k_energy<NC, NT>), dim3(f->active), dim3(kBlock), l, st, f->d, mask, eout);
+    hipLaunchKernelGGL((k_energy<NC, NT>), dim3(f->active), dim3(kBlock), l, st, d, mask, eout);
 }
 
-ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st) {
+ld_status run_energy(ld_frame f, const uint8_t* mask, float* eout, hipStream_t st, const Dev* dsel = nullptr) {
     ProfScope ps(f, 4, st);
-    const int nc = (f->d.W + kBlock - 1) / kBlock;
-    if (nc <= 1) launch_energy<1, 2>(f, mask, eout, st);
-    else if (nc <= 2) launch_energy<2, 4>(f, mask, eout, st);
-    else if (nc <= 3) launch_energy<3, 6>(f, mask, eout, st);
-    else if (nc <= 4) launch_energy<4, 8>(f, mask, eout, st);
-    else if (nc <= 5) launch_energy<5, 10>(f, mask, eout, st);
-    else if (nc <= 6) launch_energy<6, 12>(f, mask, eout, st);
-    else if (nc <= 8) launch_energy<8, 16>(f, mask, eout, st);
-    else if (nc <= 12) launch_energy<12, 24>(f, mask, eout, st);
-    else launch_energy<16, 32>(f, mask, eout, st);
+    const Dev& d = dsel ? *dsel : f->d;
+    const int nc = (d.W + kBlock - 1) / kBlock;
+    if (nc <= 1) launch_energy<1, 2>(f, d, mask, eout, st);
+    else if (nc <= 2) launch_energy<2, 4>(f, d, mask, eout, st);
+    else if (nc <= 3) launch_energy<3, 6>(f, d, mask, eout, st);
+    else if (nc <= 4) launch_energy<4, 8>(f, d, mask, eout, st);
+    else if (nc <= 5) launch_energy<5, 10>(f, d, mask, eout, st);
+    else if (nc <= 6) launch_energy<6, 12>(f, d, mask, eout, st);
+    else if (nc <= 8) launch_energy<8, 16>(f, d, mask, eout, st);
+    else if (nc <= 12) launch_energy<12, 24>(f, d, mask, eout, st);
+    else launch_energy<16, 32>(f, d, mask, eout, st);
     return launch_ok();
 }
 
-ld_status run_peaks(ld_frame f, ld_lanes* lanes, float* curves, hipStream_t st) {
+ld_status run_peaks(ld_frame f, ld_lanes* lanes, float* curves, hipStream_t st, const Dev* dsel = nullptr) {
     ProfScope ps(f, 5, st);
-    hipLaunchKernelGGL(k_peaks, dim3(f->active), dim3(kBlock), (size_t)f->d.W2, st, f->d, lanes, curves);
+    const Dev& d = dsel ? *dsel : f->d;
+    hipLaunchKernelGGL(k_peaks, dim3(f->active), dim3(kBlock), (size_t)d.W2, st, d, lanes, curves);
     return launch_ok();
 }
 
@@ -1547,9 +1895,18 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
     d.trace = reinterpret_cast<int32_t*>(base + off[11]);
     d.qbuf = reinterpret_cast<float*>(base + off[12]);
     d.rbound = reinterpret_cast<uint32_t*>(base + off[13]);
+    d.lbits = reinterpret_cast<uint8_t*>(base + off[14]);
+    d.prune = reinterpret_cast<int32_t*>(base + off[15]);
+    d.cmask = reinterpret_cast<uint8_t*>(base + off[16]);
+    d.seedg = reinterpret_cast<double*>(base + off[17]);
+    d.only = nullptr;
+    d.only_bits = 0;
+    d.only_set = 0;
     // small state starts zeroed so that introspection of an unprocessed frame is defined
     if (hipMemset(d.info, 0, sz[4]) != hipSuccess || hipMemset(d.trace, 0xff, sz[11]) != hipSuccess ||
-        hipMemset(d.fit, 0, sz[3]) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipMemset(d.fit, 0, sz[3]) != hipSuccess || hipMemset(d.prune, 0, sz[15]) != hipSuccess ||
+        hipMemset(d.lbits, 0, sz[14]) != hipSuccess || hipMemset(d.cmask, 1, sz[16]) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(f->mem);
         delete f;
         return LD_E_HIP;
@@ -1559,6 +1916,7 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
     f->active = batch;
     f->last = nullptr;
     f->stage = 0;
+    f->bands = 0;
     *out = f;
     return LD_OK;
 }
@@ -1590,6 +1948,7 @@ ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint6
     ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, vdisp_out, beta_out, st);
     f->last = st;
     if (s == LD_OK) f->stage = 1;
+    f->bands = 0;
     return s;
 }
 
@@ -1643,6 +2002,74 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
     if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st);
     if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st);
     f->stage = s == LD_OK ? 3 : 0;
+    f->bands = 0;
+    return s;
+}
+
+ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                           int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
+                           ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    if (!f || !n || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
+    if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
+    if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
+    if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
+    const ld_cnn_config* c = ldi_cnn_config(n);
+    if (!c || !(f->d.P.varpi > 0.0)) return LD_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    f->last = st;
+    Dev& d = f->d;
+    const int nb = c->n_bands;
+    ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
+    f->stage = s == LD_OK ? 1 : 0;
+    f->bands = 0;
+    if (s == LD_OK) {
+        ProfScope ps(f, 6, st);
+        s = ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, nullptr, st);
+    }
+    if (s == LD_OK) s = run_edges(f, grey, grey_pitch, disp, disp_pitch, st);
+    if (s == LD_OK) {
+        ProfScope ps(f, 7, st);
+        const size_t ls = sizeof(int) * 2 * (size_t)d.W2;
+        allow_lds(k_seed, ls);
+        hipLaunchKernelGGL(k_seed, dim3(f->active), dim3(kBlock), ls, st, d, nb, c->delta_x, c->min_votes,
+                           c->seed_ransac);
+        s = launch_ok();
+    }
+    if (s == LD_OK) {
+        ProfScope ps(f, 8, st);
+        const size_t lw = sizeof(int) * (3 * 256 + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
+        allow_lds(k_vpx_window, lw);
+        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(256), lw, st, d, stream_ids, frame_idx, nullptr);
+        s = launch_ok();
+    }
+    Dev full = d;                       // frames sent back to the full V_px search
+    full.only = d.prune;
+    full.only_bits = kFbPlainVpx;
+    full.only_set = 1;
+    if (s == LD_OK) s = run_vpx(f, full, stream_ids, frame_idx, nullptr, nullptr, st);
+    if (s == LD_OK) {
+        ProfScope ps(f, 9, st);
+        const size_t lm = sizeof(uint32_t) * nb * LDI_BAND_ROWS * (size_t)((d.W + 31) / 32) + (size_t)d.W2;
+        allow_lds(k_cand_mask, lm);
+        hipLaunchKernelGGL(k_cand_mask, dim3(f->active), dim3(kBlock), lm, st, d, nb, c->dilate);
+        s = launch_ok();
+    }
+    if (s == LD_OK) s = run_energy(f, d.cmask, nullptr, st);
+    if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st);
+    if (s == LD_OK) {
+        ProfScope ps(f, 9, st);
+        hipLaunchKernelGGL(k_lane_check, dim3((f->active + 63) / 64), dim3(64), 0, st, d, lanes_out, f->active,
+                           c->dilate >= 0 ? 1 : 0);
+        s = launch_ok();
+    }
+    Dev again = d;                      // frames sent back to the full energies
+    again.only = d.prune;
+    again.only_bits = kFbPlainEnergy;
+    again.only_set = 1;
+    if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st, &again);
+    if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st, &again);
+    f->stage = s == LD_OK ? 3 : 0;
+    if (s == LD_OK) f->bands = nb;
     return s;
 }
 
@@ -1698,6 +2125,12 @@ ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t 
         case LD_STATE_MX_PATH: src = d.mxpath + (size_t)b * d.H; n = sizeof(int32_t) * d.H; break;
         case LD_STATE_ENERGY: src = d.energy + (size_t)b * d.W2; n = sizeof(double) * d.W2; break;
         case LD_STATE_TRACE: src = d.trace + (size_t)b * 6 * kMaxRounds; n = sizeof(int32_t) * 6 * kMaxRounds; break;
+        case LD_STATE_LANE_BITS:
+            src = d.lbits + (size_t)b * LDI_MAX_BANDS * LDI_BAND_ROWS * d.W;
+            n = (size_t)LDI_MAX_BANDS * LDI_BAND_ROWS * d.W;
+            break;
+        case LD_STATE_PRUNE: src = d.prune + (size_t)b * kPruneWords; n = sizeof(int32_t) * kPruneWords; break;
+        case LD_STATE_CAND_MASK: src = d.cmask + (size_t)b * d.W2; n = (size_t)d.W2; break;
         default: return LD_E_INVAL;
     }
     if (bytes < (int64_t)n) return LD_E_INVAL;
@@ -1716,6 +2149,26 @@ ld_status ldi_frame_bind_count(ld_frame f, const int32_t* d_count) {
 }
 
 const ld_fit* ldi_frame_fits(ld_frame f) { return f ? reinterpret_cast<const ld_fit*>(f->d.fit) : nullptr; }
+
+ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v) {
+    if (!f || !v) return LD_E_INVAL;
+    const Dev& d = f->d;
+    v->W = d.W; v->H = d.H; v->fmt = d.fmt; v->d_max = d.d_max; v->batch = f->batch; v->active = f->active;
+    v->stage = f->stage;
+    v->varpi = d.P.varpi;
+    v->tab = d.tab;
+    v->info = reinterpret_cast<const int32_t*>(d.info);
+    v->lane_bits = d.lbits;
+    v->nact = d.nact;
+    return LD_OK;
+}
+
+ld_status ldi_frame_mark_bands(ld_frame f, int32_t n_bands, void* stream) {
+    if (!f) return LD_E_INVAL;
+    f->bands = n_bands;
+    f->last = static_cast<hipStream_t>(stream);
+    return LD_OK;
+}
 
 size_t ldi_frame_bytes(int32_t width, int32_t height, int32_t batch, int32_t d_max) {
     size_t off[kRegions], sz[kRegions];

@@ -2,6 +2,7 @@
 // (ld_server.hip).  Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -17,3 +18,32 @@ const ld_fit* ldi_frame_fits(ld_frame f);
 
 // Bytes of device scratch a frame object of this shape allocates.
 size_t ldi_frame_bytes(int32_t width, int32_t height, int32_t batch, int32_t d_max);
+
+// What the network kernels (ld_cnn.hip) need of a frame object.
+#define LDI_MAX_BANDS 4
+#define LDI_BAND_ROWS 16
+typedef struct {
+    int32_t W, H, fmt, d_max, batch, active, stage;
+    double varpi;
+    const double* tab;        /* batch x 6 x H: f, f', V_py, V_px, A_v, B_v */
+    const int32_t* info;      /* batch x 8: flags, v_h, ... */
+    uint8_t* lane_bits;       /* batch x LDI_MAX_BANDS x LDI_BAND_ROWS x W: network decisions */
+    const int32_t* nact;      /* nullable active-frame count on the device */
+} ldi_frame_view;
+
+ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v);
+
+// Marks that the band decisions of the frame were written on `stream` (after ld_vdisp).
+ld_status ldi_frame_mark_bands(ld_frame f, int32_t n_bands, void* stream);
+
+// First row of band k (0 = bottom) of a frame whose road starts at v_h, or -1 without bands.
+__host__ __device__ inline int ldi_band_top(int v_h, int H, int n_bands, int k) {
+    const int R = H - v_h;
+    if (R < LDI_BAND_ROWS || n_bands < 1) return -1;
+    return (H - LDI_BAND_ROWS) - ((R - LDI_BAND_ROWS) * k) / n_bands;
+}
+
+// Network decisions for the active frames of f into its band buffer (ld_cnn.hip).
+ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dp,
+                       float* prob_out, hipStream_t st);
+const ld_cnn_config* ldi_cnn_config(ld_cnn n);

@@ -21,7 +21,9 @@ LD_DISP_U8, LD_DISP_F32, LD_DISP_U16Q4 = 0, 1, 2
 LD_FLAG_NOROAD, LD_FLAG_NOVP, LD_FLAG_NOCONS_Y, LD_FLAG_NOCONS_X, LD_FLAG_FALLBACK = 1, 2, 4, 8, 16
 LD_MAX_LANES = 16
 (LD_STATE_INFO, LD_STATE_MY_PATH, LD_STATE_BETA, LD_STATE_GAMMA, LD_STATE_TABLES, LD_STATE_ROWCOUNT,
- LD_STATE_EDGES, LD_STATE_MX_PATH, LD_STATE_ENERGY, LD_STATE_TRACE) = range(10)
+ LD_STATE_EDGES, LD_STATE_MX_PATH, LD_STATE_ENERGY, LD_STATE_TRACE, LD_STATE_LANE_BITS, LD_STATE_PRUNE,
+ LD_STATE_CAND_MASK) = range(13)
+LD_CNN_PARAMS = 3057
 MAX_ROUNDS_STORED = 64
 
 
@@ -48,6 +50,12 @@ class ld_fit(C.Structure):
     _fields_ = [("ok", C.c_int32), ("flags", C.c_int32), ("center", C.c_int32), ("kshift", C.c_int32),
                 ("rounds", C.c_int32), ("n_survivors", C.c_int32),
                 ("coef", C.c_double * 5), ("raw", C.c_double * 5)]
+
+
+class ld_cnn_config(C.Structure):
+    _fields_ = [("n_bands", C.c_int32), ("theta", C.c_float), ("delta_x", C.c_int32), ("dilate", C.c_int32),
+                ("min_votes", C.c_int32), ("max_batch", C.c_int32), ("max_width", C.c_int32),
+                ("seed_ransac", C.c_int32)]
 
 
 class ld_server_config(C.Structure):
@@ -108,6 +116,20 @@ def lib():
         L.ld_server_pending.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.ld_server_engines.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.ld_frame_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32]
+        L.ld_cnn_config_default.argtypes = [C.POINTER(ld_cnn_config)]
+        L.ld_cnn_config_default.restype = None
+        fp = C.POINTER(C.c_float)
+        L.ld_cnn_create.argtypes = [C.POINTER(ld_cnn_config), fp, C.POINTER(vp)]
+        L.ld_cnn_destroy.argtypes = [vp]
+        L.ld_cnn_set_params.argtypes = [vp, fp]
+        L.ld_cnn_get_params.argtypes = [vp, fp]
+        L.ld_cnn_forward.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
+        L.ld_cnn_labels.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp, vp]
+        L.ld_cnn_train_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp]
+        L.ld_detect_pruned.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
+                     "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"):
+            getattr(L, name).restype = i32
         for name in ("ld_server_create", "ld_server_destroy", "ld_server_submit", "ld_server_poll",
                      "ld_server_pending", "ld_server_engines", "ld_frame_profile", "ld_frame_kernel_times", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp", "ld_vp_ransac",
                      "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_frame_read"):
@@ -119,8 +141,11 @@ def lib():
 EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_frame_set_active", "ld_vdisp",
             "ld_vp_ransac", "ld_lane_energy", "ld_peaks", "ld_detect", "ld_sync", "ld_status_string",
             "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times", "ld_server_create", "ld_server_destroy",
-            "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines"]
-KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks"]
+            "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
+            "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
+            "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"]
+KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
+           "k_vpx_window", "k_cand_mask"]
 
 
 def check(status: int, what: str = "ld call"):
@@ -232,6 +257,55 @@ def ld_server_engines(s):
     b = C.c_int64(0)
     st = lib().ld_server_engines(s, pc, C.byref(b))
     return st, list(pc), b.value
+
+
+def ld_cnn_config_default(c: ld_cnn_config) -> None:
+    lib().ld_cnn_config_default(C.byref(c))
+
+
+def ld_cnn_create(cfg, params):
+    h = C.c_void_p()
+    st = lib().ld_cnn_create(C.byref(cfg) if cfg is not None else None, params, C.byref(h))
+    return st, h
+
+
+def ld_cnn_destroy(n):
+    return lib().ld_cnn_destroy(n)
+
+
+def ld_cnn_set_params(n, params):
+    return lib().ld_cnn_set_params(n, params)
+
+
+def ld_cnn_get_params(n, params):
+    return lib().ld_cnn_get_params(n, params)
+
+
+def ld_cnn_forward(n, f, grey, grey_pitch, disp, disp_pitch, prob_out, stream):
+    return lib().ld_cnn_forward(n, f, grey, grey_pitch, disp, disp_pitch, prob_out, stream)
+
+
+def ld_cnn_labels(n, f, lanes, curves, radius, radius_per_disp, labels_out, stream):
+    return lib().ld_cnn_labels(n, f, lanes, curves, radius, radius_per_disp, labels_out, stream)
+
+
+def ld_cnn_train_step(n, f, grey, grey_pitch, disp, disp_pitch, labels, pos_weight, inv_norm, lr, loss_out,
+                      grad_out, stream):
+    return lib().ld_cnn_train_step(n, f, grey, grey_pitch, disp, disp_pitch, labels, pos_weight, inv_norm, lr,
+                                   loss_out, grad_out, stream)
+
+
+def ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out, stream):
+    return lib().ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out,
+                                  curves_out, stream)
+
+
+def cnn_config(**overrides) -> ld_cnn_config:
+    c = ld_cnn_config()
+    lib().ld_cnn_config_default(C.byref(c))
+    for k, v in overrides.items():
+        setattr(c, k, v)
+    return c
 
 
 def server_config(classes, *, n_streams=32, inflight=2, max_queue=256, use_graphs=True, seed_from_state=True,
@@ -383,6 +457,11 @@ class Detector:
     def parse_lanes(buf) -> np.ndarray:
         return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=LANES_DTYPE)
 
+    def detect_pruned(self, net: "Cnn", grey, disp, lanes_out, stream_ids=None, frame_idx=None, curves_out=None):
+        check(ld_detect_pruned(self.handle, net.handle, _ptr(grey), self._pitch(grey), _ptr(disp), self._pitch(disp),
+                               _ptr(stream_ids), _ptr(frame_idx), _ptr(lanes_out), _ptr(curves_out), _stream()),
+              "ld_detect_pruned")
+
     def read(self, what: int, b: int = 0) -> np.ndarray:
         """Copy one piece of frame b's device state to the host (synchronous)."""
         import torch
@@ -392,6 +471,8 @@ class Detector:
             LD_STATE_GAMMA: (FIT_DTYPE, 1), LD_STATE_TABLES: (np.float64, 6 * H), LD_STATE_ROWCOUNT: (np.int32, H),
             LD_STATE_EDGES: (EDGE_DTYPE, H * W), LD_STATE_MX_PATH: (np.int32, H),
             LD_STATE_ENERGY: (np.float64, 2 * W), LD_STATE_TRACE: (np.int32, 6 * MAX_ROUNDS_STORED),
+            LD_STATE_LANE_BITS: (np.uint8, 4 * 16 * W), LD_STATE_PRUNE: (np.int32, 16),
+            LD_STATE_CAND_MASK: (np.uint8, 2 * W),
         }[what]
         dt = np.dtype(spec[0])
         nbytes = dt.itemsize * spec[1]
@@ -399,3 +480,53 @@ class Detector:
         check(ld_frame_read(self.handle, what, b, C.c_void_p(host.data_ptr()), nbytes, _stream()), "ld_frame_read")
         torch.cuda.current_stream().synchronize()
         return np.frombuffer(host.numpy().tobytes(), dtype=dt)
+
+
+class Cnn:
+    """The candidate-pruning network (ld_cnn_*).  Parameters are host float32 arrays of
+    LD_CNN_PARAMS values in the order of include/ld.h."""
+
+    def __init__(self, params=None, **config):
+        self.config = cnn_config(**config)
+        p = None
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32)
+            assert arr.size == LD_CNN_PARAMS
+            p = arr.ctypes.data_as(C.POINTER(C.c_float))
+        st, h = ld_cnn_create(self.config, p)
+        check(st, "ld_cnn_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ld_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        assert arr.size == LD_CNN_PARAMS
+        check(ld_cnn_set_params(self.handle, arr.ctypes.data_as(C.POINTER(C.c_float))), "ld_cnn_set_params")
+
+    def get_params(self) -> np.ndarray:
+        arr = np.zeros(LD_CNN_PARAMS, np.float32)
+        check(ld_cnn_get_params(self.handle, arr.ctypes.data_as(C.POINTER(C.c_float))), "ld_cnn_get_params")
+        return arr
+
+    def forward(self, det: Detector, grey, disp, prob_out=None):
+        check(ld_cnn_forward(self.handle, det.handle, _ptr(grey), det._pitch(grey), _ptr(disp), det._pitch(disp),
+                             _ptr(prob_out), _stream()), "ld_cnn_forward")
+
+    def labels(self, det: Detector, lanes, curves, labels_out, radius=2.0, radius_per_disp=0.139):
+        check(ld_cnn_labels(self.handle, det.handle, _ptr(lanes), _ptr(curves), radius, radius_per_disp,
+                            _ptr(labels_out), _stream()), "ld_cnn_labels")
+
+    def train_step(self, det: Detector, grey, disp, labels, pos_weight, inv_norm, lr, loss_out=None, grad_out=None):
+        check(ld_cnn_train_step(self.handle, det.handle, _ptr(grey), det._pitch(grey), _ptr(disp), det._pitch(disp),
+                                _ptr(labels), pos_weight, inv_norm, lr, _ptr(loss_out), _ptr(grad_out), _stream()),
+              "ld_cnn_train_step")
