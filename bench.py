@@ -36,9 +36,9 @@ def _gen(args):
     return g, d
 
 
-def make_workload(n_seq: int, per_seq: int, procs: int):
+def make_workload(n_seq: int, per_seq: int, procs: int, first_seq: int = 0):
     from concurrent.futures import ProcessPoolExecutor
-    jobs = [(s, i, 16) for s in range(n_seq) for i in range(0, per_seq, 16)]
+    jobs = [(s, i, min(16, per_seq - i)) for s in range(first_seq, first_seq + n_seq) for i in range(0, per_seq, 16)]
     greys, disps = [], []
     with ProcessPoolExecutor(max_workers=procs) as ex:
         for g, d in ex.map(_gen, jobs):
@@ -66,6 +66,130 @@ def measured_traffic(kernel: str):
     if h.hexdigest() != rec["source_sha256"]:
         return None
     return rec["bytes_per_launch"].get(kernel)
+
+
+SERVE_CLASSES = [(640, 192, 0, 96, 16), (1242, 375, 0, 128, 16), (1920, 1080, 0, 255, 16)]
+SERVE_STREAMS, SERVE_FPS, SERVE_POOL = 32, 30.0, 4
+
+
+def _gen_serving(args):
+    from paper_1807_02752_amd import synth
+    stream, cls = args
+    W, H, _, dm, _ = SERVE_CLASSES[cls]
+    return [synth.make_scaled_c1(W, H, dm, seed=100 + stream, idx=i)[:2] for i in range(SERVE_POOL)]
+
+
+def make_serving_pool(procs: int):
+    """32 camera streams, each of a resolution class drawn uniformly (seeded), with a few
+    u8 frames of the scaled 320x96 generator per stream, cycled by the arrivals."""
+    from concurrent.futures import ProcessPoolExecutor
+    rng = np.random.default_rng(7)
+    classes = rng.integers(0, len(SERVE_CLASSES), SERVE_STREAMS).tolist()
+    with ProcessPoolExecutor(max_workers=procs) as ex:
+        frames = list(ex.map(_gen_serving, list(enumerate(classes))))
+    return classes, frames
+
+
+def serving_leg(args, pool):
+    """Continuous batching: every stream submits frames as Poisson arrivals at 30 fps for
+    serve_seconds of wall time while the host polls; latency is arrival to host-visible
+    result."""
+    import torch
+    from paper_1807_02752_amd import ld
+    classes, frames = pool
+    dev = [[(torch.from_numpy(gr).cuda(), torch.from_numpy(dp).cuda()) for gr, dp in fr] for fr in frames]
+    cfg = ld.server_config(SERVE_CLASSES, n_streams=SERVE_STREAMS, inflight=2, max_queue=1024, use_graphs=True)
+    srv = ld.Server(cfg)
+    rng = np.random.default_rng(11)
+    T = args.serve_seconds
+    arrivals = []
+    for s in range(SERVE_STREAMS):
+        t = rng.exponential(1.0 / SERVE_FPS)
+        while t < T:
+            arrivals.append((t, s))
+            t += rng.exponential(1.0 / SERVE_FPS)
+    arrivals.sort()
+    # warm-up: one frame of every class through the server (graph capture happens here)
+    for c in range(len(SERVE_CLASSES)):
+        s = classes.index(c) if c in classes else None
+        if s is not None:
+            srv.submit(s, c, *dev[s][0])
+    while sum(srv.pending()) > 0:
+        srv.poll()
+    lat, done, k = [], 0, 0
+    count = {s: 0 for s in range(SERVE_STREAMS)}
+    t0 = time.perf_counter()
+    while k < len(arrivals) or sum(srv.pending()) > 0:
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k][0] <= now:
+            s = arrivals[k][1]
+            gr, dp = dev[s][count[s] % SERVE_POOL]
+            count[s] += 1
+            st, _ = srv.submit(s, classes[s], gr, dp)
+            assert st == ld.LD_OK, st
+            k += 1
+        for r in srv.poll():
+            lat.append((r["t_done"] - r["t_submit"]) * 1e3)
+            done += 1
+    wall = time.perf_counter() - t0
+    pc, mem = srv.engines()
+    srv.close()
+    lat = np.array(lat)
+    return {"streams": SERVE_STREAMS, "offered_fps": len(arrivals) / T, "achieved_fps": done / wall,
+            "requests": done, "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "classes": [f"{w}x{h}" for w, h, *_ in SERVE_CLASSES], "streams_per_class": [classes.count(c) for c in range(3)],
+            "engines_per_class": pc[:3], "engine_bytes": mem, "graphs": True, "pruning": False}
+
+
+def learned_leg(args, det, g, d, lanes, plain_lanes, tgreys, tdisps, plain_ms):
+    """Train the pruning network on the GPU (frames of other sequences, labels from the plain
+    search), then time ld_detect_pruned on the same batch and compare its lanes with the plain
+    search's."""
+    import torch
+    from paper_1807_02752_amd import ld
+    from paper_1807_02752_amd import train as tr
+    B = g.shape[0]
+    t0 = time.time()
+    G, D = torch.from_numpy(tgreys).cuda(), torch.from_numpy(tdisps).cuda()
+    net, losses = tr.train(G, D, 128, steps=args.train_steps, batch=16, lr=3e-3, pos_weight=4.0, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    del G, D
+    log(f"trained {args.train_steps} steps in {train_s:.1f}s, loss {losses[:10].mean():.4f} -> {losses[-10:].mean():.4f}")
+    lp = det.lanes_buffer()
+    for _ in range(args.warmup):
+        det.detect_pruned(net, g, d, lp)
+    torch.cuda.synchronize()
+    det.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        det.detect_pruned(net, g, d, lp)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    kt = det.kernel_times()
+    det.profile(False)
+    L = ld.Detector.parse_lanes(lp)
+    diff = tot = 0
+    for a, b in zip(plain_lanes, L):
+        sa, sb = set(a["u_start"][: a["n"]].tolist()), set(b["u_start"][: b["n"]].tolist())
+        diff += len(sa ^ sb)
+        tot += len(sa)
+    fb = [det.read(ld.LD_STATE_PRUNE, b)[1] for b in range(B)]
+    cfg = net.config
+    res = {"value": B / (ms / 1e3), "unit": "frames/s", "ms_per_step": ms, "speedup_vs_plain": plain_ms / ms,
+           "lane_disagreement": diff / max(tot, 1), "lanes_compared": tot,
+           "fallback_frac": float(np.mean([(x & 3) != 0 for x in fb])),
+           "kernels_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in kt.items() if v[1]},
+           "network": {"n_bands": cfg.n_bands, "theta": round(cfg.theta, 3), "delta_x": cfg.delta_x,
+                       "dilate": cfg.dilate, "seed_ransac": cfg.seed_ransac, "params": ld.LD_CNN_PARAMS},
+           "train": {"steps": args.train_steps, "batch": 16, "frames": int(tgreys.shape[0]), "seconds": round(train_s, 2),
+                     "loss_first10": float(losses[:10].mean()), "loss_last10": float(losses[-10:].mean())}}
+    net.close()
+    log(f"pruned: {ms:.3f} ms/step ({plain_ms / ms:.2f}x plain), disagreement {res['lane_disagreement']:.4f}, "
+        f"fallback {res['fallback_frac']:.3f}")
+    return res
 
 
 def cpu_baseline(greys, disps, seconds: float, threads: int):
@@ -104,6 +228,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--train-steps", type=int, default=300, help="training steps of the pruning network (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving run (0: skip)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (4 launches) to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -129,6 +255,9 @@ def main():
     t0 = time.time()
     greys, disps = make_workload(args.sequences, args.per_seq, args.procs)
     B, H, W = greys.shape
+    if args.train_steps > 0:     # training frames: other sequences than the timed workload
+        tgreys, tdisps = make_workload(16, 16, args.procs, first_seq=1000)
+    serve_pool = make_serving_pool(args.procs) if args.serve_seconds > 0 else None
     log(f"generated {B} frames {W}x{H} in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
@@ -221,6 +350,10 @@ def main():
         "lanes_per_frame": float(lanes_np["n"].mean()),
         "learned_pruned": None,
     }
+    if args.train_steps > 0:
+        out["learned_pruned"] = learned_leg(args, det, g, d, lanes, lanes_np, tgreys, tdisps, ms_per_step)
+    if serve_pool is not None:
+        out["serving"] = serving_leg(args, serve_pool)
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(greys, disps, args.cpu_seconds, threads)

@@ -194,29 +194,41 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
                 for (int p = 0; p <= DEG; ++p) model[p] = seed_raw[p];
                 kind = 2;
             } else {
+                // draw indices until s distinct ones; the picks stay in registers (every
+                // array index below is static after unrolling)
                 int pick[s];
+#pragma unroll
+                for (int e = 0; e < s; ++e) pick[e] = -1;
                 int got = 0;
                 for (int blk = 0; blk < 16 && got < s; ++blk) {
                     U64x4 w = philox4x64_10(ctr0, ((uint64_t)stage << 32) | (uint64_t)(uint32_t)r, (uint64_t)t,
                                             (uint64_t)blk, P.seed, key1);
-                    for (int q = 0; q < 4 && got < s; ++q) {
-                        int ix = (int)__umul64hi(w.w[q], (uint64_t)n_cur);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int ix = (int)__umul64hi(w.w[q], (uint64_t)n_cur);
                         bool dup = false;
-                        for (int e = 0; e < got; ++e) dup = dup || (pick[e] == ix);
-                        if (!dup) pick[got++] = ix;
+#pragma unroll
+                        for (int e = 0; e < s; ++e) dup = dup || (e < got && pick[e] == ix);
+                        const bool take = got < s && !dup;
+#pragma unroll
+                        for (int e = 0; e < s; ++e) pick[e] = (take && e == got) ? ix : pick[e];
+                        got += take ? 1 : 0;
                     }
                 }
                 if (got == s) {
-                    int distinct = 0;
-                    for (int e = 0; e < s; ++e) {
-                        bool seen = false;
-                        for (int f = 0; f < e; ++f) seen = seen || (X[cur[pick[f]]] == X[cur[pick[e]]]);
-                        distinct += seen ? 0 : 1;
-                    }
-                    if (distinct == s) {
+                    int px[s], py[s];
+#pragma unroll
+                    for (int e = 0; e < s; ++e) { px[e] = X[cur[pick[e]]]; py[e] = Y[cur[pick[e]]]; }
+                    bool distinct = true;
+#pragma unroll
+                    for (int e = 1; e < s; ++e)
+#pragma unroll
+                        for (int f = 0; f < e; ++f) distinct = distinct && (px[f] != px[e]);
+                    if (distinct) {
                         Moments M;
                         moments_zero(M);
-                        for (int e = 0; e < s; ++e) moments_add<DEG>(M, X[cur[pick[e]]], Y[cur[pick[e]]], center);
+#pragma unroll
+                        for (int e = 0; e < s; ++e) moments_add<DEG>(M, px[e], py[e], center);
                         kind = solve_moments<DEG>(M, k, model) ? 1 : 0;
                     }
                 }
@@ -230,13 +242,24 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
             const int h = lane;
             int cnt = -1;
             if (h < n_hyp && S.mvalid[h] != 0) {
-                cnt = 0;
-                const double* m = S.models[h];
+                double m[5];
+#pragma unroll
+                for (int p = 0; p < 5; ++p) m[p] = S.models[h][p];
                 const int kind = S.mvalid[h];
-                for (int jj = wave; jj < n_cur; jj += nw) {
-                    int j = cur[jj];
-                    cnt += is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr) ? 1 : 0;
+                int c4[4] = {0, 0, 0, 0};
+                int jj = wave;
+                for (; jj + 3 * nw < n_cur; jj += 4 * nw) {   // four independent evaluations
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = cur[jj + u * nw];
+                        c4[u] += is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr) ? 1 : 0;
+                    }
                 }
+                for (; jj < n_cur; jj += nw) {
+                    const int j = cur[jj];
+                    c4[0] += is_inlier<DEG>(m, kind, center, k, X[j], Y[j], tr) ? 1 : 0;
+                }
+                cnt = (c4[0] + c4[1]) + (c4[2] + c4[3]);
             }
             S.counts[wave][h] = cnt;
         }
@@ -1387,7 +1410,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 // that the path never reaches an inner edge of the window, then the fit.  One workgroup of
 // 256 threads per frame (one window column each); the backtrace (int8 per row and window
 // column) uses the frame's backtrace buffer.
-__global__ __launch_bounds__(256) void k_vpx_window(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+__global__ __launch_bounds__(256, 4) void k_vpx_window(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
                                                     double* vp_out) {
     extern __shared__ unsigned char smem[];
     __shared__ RansacShared S;
@@ -1408,10 +1431,12 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, const uint64_t* strea
     }
     const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
     const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
-    int* hist = reinterpret_cast<int*>(smem);   // 256
-    int* Ea = hist + 256;
-    int* Eb = Ea + 256;
-    int* PX = Eb + 256;
+    // LDS: two delta rows of the band histogram (ping-pong by row), two DP rows with 5 guard
+    // columns of kBig on each side, the fit scratch
+    int* dlt = reinterpret_cast<int*>(smem);    // 2 x 256
+    int* Ea = dlt + 512;                         // 266
+    int* Eb = Ea + 266;                          // 266
+    int* PX = Eb + 266;
     int* PY = PX + H;
     int* cur = PY + H;
     int* cur2 = cur + H;
@@ -1420,48 +1445,95 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, const uint64_t* strea
     const int bm_words = (H + 31) / 32;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
     for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
-    for (int i = t; i < 256; i += nt) hist[i] = 0;
+    for (int i = t; i < 512; i += nt) dlt[i] = 0;
+    for (int i = t; i < 266; i += nt) { Ea[i] = kBig; Eb[i] = kBig; }
     __syncthreads();
     int ne = 0;
     for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
     ne = block_sum_i32(ne, S.red);
     int nv = 0;
-    auto apply = [&](int r, int sign, bool count) {
+    // the initial band, then the column count of thread t's own window column lives in h
+    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) {
         const int n = cntL[r];
         for (int i = t; i < n; i += nt) {
             const int c = fe[(int64_t)r * d.W + i].bin;
-            if (count && c >= 0) ++nv;
-            if (c >= lo && c <= hi) atomicAdd(&hist[c - lo], sign);
+            nv += c >= 0 ? 1 : 0;
+            if (c >= lo && c <= hi) atomicAdd(&dlt[c - lo], 1);
         }
+    }
+    __syncthreads();
+    int h = 0;
+    if (t < win) { h = dlt[t]; dlt[t] = 0; Ea[5 + t] = -h; }
+    __syncthreads();
+    // vote columns of the rows entering (v - chi) and leaving (v + chi + 1) at DP row v, two
+    // per thread, loaded kAhead rows ahead into a register ring; rows with more than 2 nt
+    // edges finish in a loop
+    constexpr int kAhead = 2;
+    auto load2 = [&](int r, bool ok, int* c2) {
+        const int n = ok ? cntL[r] : 0;
+        c2[0] = t < n ? fe[(int64_t)r * d.W + t].bin : -1;
+        c2[1] = t + nt < n ? fe[(int64_t)r * d.W + t + nt].bin : -1;
     };
-    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1, true);
-    __syncthreads();
-    if (t < win) Ea[t] = -hist[t];
-    __syncthreads();
+    auto load_row = [&](int v, int* a2, int* r2) {   // the bins DP row v needs (none beyond v_h)
+        const int ra = v - chi, rr = v + chi + 1;
+        load2(max(ra, 0), v >= v_h && ra >= v_h, a2);
+        load2(min(rr, v_max), v >= v_h && rr <= v_max, r2);
+    };
+    int na[kAhead][2], nr[kAhead][2];
+#pragma unroll
+    for (int k = 0; k < kAhead; ++k) load_row(v_max - 1 - k, na[k], nr[k]);
     const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
     int8_t* back = reinterpret_cast<int8_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 4;
     int* E = Ea;
     int* En = Eb;
     for (int v = v_max - 1; v >= v_h; --v) {
-        if (v - chi >= v_h) apply(v - chi, 1, true);
-        if (v + chi + 1 <= v_max) apply(v + chi + 1, -1, false);
+        int* D = dlt + (v & 1) * 256;
+        const int ra = v - chi, rr = v + chi + 1;
+        int ca[2], cr[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) { ca[k] = na[0][k]; cr[k] = nr[0][k]; }
+#pragma unroll
+        for (int j = 0; j + 1 < kAhead; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) { na[j][k] = na[j + 1][k]; nr[j][k] = nr[j + 1][k]; }
+        load_row(v - kAhead, na[kAhead - 1], nr[kAhead - 1]);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            nv += ca[k] >= 0 ? 1 : 0;
+            if (ca[k] >= lo && ca[k] <= hi) atomicAdd(&D[ca[k] - lo], 1);
+            if (cr[k] >= lo && cr[k] <= hi) atomicAdd(&D[cr[k] - lo], -1);
+        }
+        if (ra >= v_h)
+            for (int i = t + 2 * nt; i < cntL[ra]; i += nt) {
+                const int c = fe[(int64_t)ra * d.W + i].bin;
+                nv += c >= 0 ? 1 : 0;
+                if (c >= lo && c <= hi) atomicAdd(&D[c - lo], 1);
+            }
+        if (rr <= v_max)
+            for (int i = t + 2 * nt; i < cntL[rr]; i += nt) {
+                const int c = fe[(int64_t)rr * d.W + i].bin;
+                if (c >= lo && c <= hi) atomicAdd(&D[c - lo], -1);
+            }
         __syncthreads();
         if (t < win) {
-            int best = E[t], bt = 0;
+            h += D[t];
+            D[t] = 0;
+            const int* e = E + 5 + t;
+            int best = e[0], bt = 0;
             for (int a = 1; a <= tau_max; ++a) {
-                const int cl = t - a, cr = t + a;
-                if (cl >= 0 && E[cl] + lam * a < best) { best = E[cl] + lam * a; bt = -a; }
-                if (cr < win && E[cr] + lam * a < best) { best = E[cr] + lam * a; bt = a; }
+                const int l = e[-a] + lam * a, r = e[a] + lam * a;
+                if (l < best) { best = l; bt = -a; }
+                if (r < best) { best = r; bt = a; }
             }
-            En[t] = -hist[t] + best;
+            En[5 + t] = -h + best;
             back[(int64_t)(v - v_h) * win + t] = (int8_t)bt;
         }
-        __syncthreads();
         int* tmp = E; E = En; En = tmp;
     }
+    __syncthreads();
     int64_t bv = INT64_MAX;
     int bc = 0x7fffffff;
-    if (t < win) { bv = E[t]; bc = t; }
+    if (t < win) { bv = E[5 + t]; bc = t; }
     block_argmin_i64(bv, bc, rv, ri);
     if (t == 0) {
         int c = bc, touch = 0;
@@ -2037,7 +2109,7 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     }
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
-        const size_t lw = sizeof(int) * (3 * 256 + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
+        const size_t lw = sizeof(int) * (512 + 2 * 266 + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
         allow_lds(k_vpx_window, lw);
         hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(256), lw, st, d, stream_ids, frame_idx, nullptr);
         s = launch_ok();

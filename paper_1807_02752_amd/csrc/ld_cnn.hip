@@ -146,6 +146,22 @@ __device__ __forceinline__ void zero_lds(uint4* p, int n16) {
     for (int i = threadIdx.x; i < n16; i += kT) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// The cells of an activation buffer that the layers read but never write: the zero rows 0
+// and 17 and columns 66..68 of the band rows (layer 1 writes x = 2..65, layer 2 reads up to
+// x = 67, layer 3 up to x = 68).  Two uint4 per cell.
+__device__ __forceinline__ void zero_act_border(uint16_t* act) {
+    uint4* p = reinterpret_cast<uint4*>(act);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < 2 * kXW * 2; i += kT) {            // rows 0 and 17
+        const int row = i < kXW * 2 ? 0 : kLR - 1;
+        p[row * kXW * 2 + i % (kXW * 2)] = z;
+    }
+    for (int i = threadIdx.x; i < kBR * 3 * 2; i += kT) {            // rows 1..16, x = 66..68
+        const int row = 1 + i / 6, x = 66 + (i % 6) / 2;
+        p[(row * kXW + x) * 2 + (i & 1)] = z;
+    }
+}
+
 // Layer 1 (4 -> 16): 64 tiles (16 rows x 4), 16 per wave; writes ReLU(z1) as BF16 to a1 at
 // x = 2 .. 65, zero outside the frame.
 __device__ void layer1(const uint16_t* feat, uint16_t* a1, const Net& N, int u0, int W) {
@@ -264,7 +280,7 @@ __global__ __launch_bounds__(kT) void k_cnn_fwd(ldi_frame_view V, Net N, int nb,
     zero_lds(smem4, kFeatElems / 8);
     build_features(V, b, top, u0, grey, gp, disp, dp, feat, reinterpret_cast<unsigned char*>(act));   // staged in act
     __syncthreads();
-    zero_lds(reinterpret_cast<uint4*>(act), kActElems / 8);
+    zero_act_border(act);
     __syncthreads();
     layer1(feat, act, N, u0, W);
     __syncthreads();
@@ -702,7 +718,7 @@ extern "C" {
 
 void ld_cnn_config_default(ld_cnn_config* c) {
     if (!c) return;
-    c->n_bands = 2;
+    c->n_bands = 1;
     c->theta = 0.5f;
     c->delta_x = 112;
     c->dilate = -1;

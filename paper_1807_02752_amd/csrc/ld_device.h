@@ -119,15 +119,20 @@ __device__ __forceinline__ void moments_zero(Moments& M) {
     for (int p = 0; p < 5; ++p) M.syw[p] = 0;
 }
 
+// |w| < 2^12 and |y| < 2^14 (frames of at most 4096 rows and columns): w^p fits in int64 up
+// to p = 5 and y w^p up to p = 4; the higher powers are exact 64 x 64 -> 128-bit products.
 template <int DEG>
 __device__ __forceinline__ void moments_add(Moments& M, int x, int y, int center) {
-    i128 w = (i128)(x - center);
-    i128 pw = 1;
+    const int64_t w = x - center;
+    int64_t pw[6];
+    pw[0] = 1;
+#pragma unroll
+    for (int p = 1; p <= 5; ++p) pw[p] = pw[p - 1] * w;
 #pragma unroll
     for (int p = 0; p <= 2 * DEG; ++p) {
-        M.sw[p] += pw;
-        if (p <= DEG) M.syw[p] += pw * (i128)y;
-        pw *= w;
+        if (p <= 5) M.sw[p] += (i128)pw[p];
+        else M.sw[p] += (i128)pw[4] * (i128)pw[p - 4];
+        if (p <= DEG) M.syw[p] += (i128)(pw[p] * (int64_t)y);
     }
 }
 

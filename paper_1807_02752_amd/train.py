@@ -52,7 +52,7 @@ def make_labels(net: ld.Cnn, greys, disps, d_max: int, fmt: int, batch: int, rad
 
 
 def train(greys, disps, d_max: int, *, steps: int, batch: int = 16, lr: float = 3e-3, pos_weight: float = 4.0,
-          seed: int = 0, n_bands: int = 2, fmt: int = ld.LD_DISP_F32, params=None, **cnn_config):
+          seed: int = 0, n_bands: int = 1, fmt: int = ld.LD_DISP_F32, params=None, **cnn_config):
     """Train on device-resident frames greys/disps (torch uint8 / disparity tensors [N, H, W]).
     Minibatches are consecutive runs of `batch` frames, visited in a seeded random order each
     epoch.  Returns (network, per-step losses as a numpy array)."""

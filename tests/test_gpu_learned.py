@@ -376,7 +376,7 @@ def test_trained_network_gain():
     print(f"plain {times['plain']:.3f} ms, pruned {times['pruned']:.3f} ms per {B} frames; "
           f"disagreement {dis:.4f}; fallback {fb:.3f}; kept candidates {kept:.0f} of {2 * W}")
     # the same network with candidate pruning on (reported, not held to the bar)
-    net_c = ld.Cnn(net.get_params(), n_bands=2, dilate=8)
+    net_c = ld.Cnn(net.get_params(), n_bands=1, dilate=8)
     det.detect_pruned(net_c, g, d, ll)
     torch.cuda.synchronize()
     print(f"with candidate pruning (dilate 8): disagreement {lane_disagreement(P, ld.Detector.parse_lanes(ll)):.4f}")
