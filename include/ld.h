@@ -222,9 +222,10 @@ ld_status ld_frame_read(ld_frame f, int32_t what, int32_t b, void* dst, int64_t 
 /* Kernel timing (tracing aid).  ld_frame_profile(f, 1) waits for the frame's last stream,
  * clears the accumulated times and brackets every following kernel launch with a pair of
  * HIP events recorded on the launch stream; 0 turns it off.  ld_frame_kernel_times waits
- * for the recorded events and writes, for the first n of the six kernels (0 v-disparity
- * histogram, 1 v-disparity DP + RANSAC, 2 edges and votes, 3 V_px accumulator, DP and
- * RANSAC, 4 energies, 5 peaks), the total milliseconds and launch counts (calls_out
+ * for the recorded events and writes, for the first n of the eleven kernels (0 v-disparity
+ * histogram, 1 v-disparity DP + RANSAC, 2 edges and votes, 3 V_px accumulator and row DP,
+ * 4 energies, 5 peaks, 6 network decisions, 7 seed, 8 windowed V_px DP, 9 candidate mask
+ * and fallback check, 10 V_px RANSAC), the total milliseconds and launch counts (calls_out
  * nullable) since profiling was enabled. */
 ld_status ld_frame_profile(ld_frame f, int32_t enable);
 ld_status ld_frame_kernel_times(ld_frame f, double* ms_out, int64_t* calls_out, int32_t n);

@@ -8,7 +8,8 @@
 //   k_vdisp_hist   S1   v-disparity histogram (LDS bins, wave-aggregated atomics)
 //   k_vdisp_fit    S2-3 DP on the v-disparity map, RANSAC road profile, V_py, road rows
 //   k_edges        S4-5 Sobel on road rows, road mask, V_px vote column per edge
-//   k_vpx_fit      S6-8 sliding band accumulator, row DP, RANSAC V_px, track tables
+//   k_vpx_fit      S6-7 sliding band accumulator, row DP
+//   k_vpx_ransac   S8   RANSAC V_px, track tables
 //   k_energy       S9-12 w_g, M_0, M_1 row ring, candidate-by-row energy accumulation
 //   k_peaks        S13  minima, threshold, suppression, lane curves
 #include <hip/hip_runtime.h>
@@ -819,11 +820,11 @@ __host__ __device__ __forceinline__ int vpx_walk_words_dev(int W2) {
 
 __device__ __forceinline__ int rank_to_tau(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
 
-// S8 tail shared by the full and the windowed V_px search: RANSAC of the quartic through the
-// path points (PX = rows, PY = u columns), V_px and the track tables, frame info.
+// S8: RANSAC of the quartic through the path points (PX = rows, PY = u columns), V_px and the
+// track tables, frame info.
 __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int* cur, int* cur2, uint32_t* bitmap,
                              int bm_words, RansacShared& S, const uint64_t* stream_ids, const int64_t* frame_idx,
-                             const double* seed, double* vp_out, int ne, int nv) {
+                             const double* seed, double* vp_out) {
     const int t = threadIdx.x, nt = blockDim.x;
     const int H = d.H, v_max = H - 1, v_h = fi.v_h, R = v_max - v_h + 1;
     double* tf = d.tab + (int64_t)b * 6 * H;
@@ -857,13 +858,10 @@ __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int*
         }
     }
     bad = block_max_i32(bad, S.red);
-    nv = block_sum_i32(nv, S.red);
     if (t == 0) {
         fi.flags |= (g.flags & 1) ? LD_FLAG_NOCONS_X : 0;
         if (!g.ok) fi.flags |= LD_FLAG_NOVP;
         fi.v_end = g.ok ? bad + 1 : H;
-        fi.n_edges = ne;
-        fi.n_votes = nv;
         fi.n_mx = R;
         d.info[b] = fi;
     }
@@ -877,37 +875,19 @@ __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int*
 }
 
 template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
-                                                  const double* seed_gamma, double* vp_out) {
+__global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d) {
     extern __shared__ unsigned char smem[];
-    __shared__ RansacShared S;
     __shared__ int64_t rv[kMaxWaves];
     __shared__ int ri[kMaxWaves];
+    __shared__ int red[kMaxWaves];
     __shared__ int s_c;
     const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
     if (frame_masked(d, b)) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
     const int nwords = (W2 + kDpRun - 1) / kDpRun;
     FrameInfo fi = d.info[b];
-    double* tf = d.tab + (int64_t)b * 6 * H;
-    double* tvpy = tf + 2 * H;
-    double* tvpx = tf + 3 * H;
-    double* tA = tf + 4 * H;
-    double* tB = tf + 5 * H;
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    for (int v = t; v < H; v += nt) {
-        tA[v] = 0.0;
-        tB[v] = 0.0;
-        d.mxpath[(int64_t)b * H + v] = -1;
-    }
-    if (fi.flags & LD_FLAG_NOROAD) {
-        if (vp_out)
-            for (int v = t; v < H; v += nt) {
-                vp_out[((int64_t)b * H + v) * 2] = nan;
-                vp_out[((int64_t)b * H + v) * 2 + 1] = nan;
-            }
-        return;
-    }
+    for (int v = t; v < H; v += nt) d.mxpath[(int64_t)b * H + v] = -1;
+    if (fi.flags & LD_FLAG_NOROAD) return;
     const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
     // DP rows and the band histogram are stored run-interleaved, column c at
     // (c mod 8) * NR + c / 8 + 1, so that the lanes of a wave (one run of 8 columns each)
@@ -917,13 +897,7 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
     int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved
     int* Sa = hist + WP;                 // E << 4
     int* Sb = Sa + WP;
-    int* PX = Sb + WP;
-    int* PY = PX + H;
-    int* cur = PY + H;
-    int* cur2 = cur + H;
-    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + H);
-    const int bm_words = (H + 31) / 32;
-    uint32_t* win = bitmap + bm_words;   // kWalkRows x walk-window words
+    uint32_t* win = reinterpret_cast<uint32_t*>(Sb + WP);   // kWalkRows x walk-window words
     int* cntL = reinterpret_cast<int*>(win + vpx_walk_words_dev(W2));   // per-row edge counts
     const ld_edge* fedges = d.edges + (int64_t)b * H * d.W;
     for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
@@ -931,7 +905,7 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
     __syncthreads();
     int ne = 0;
     for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
-    ne = block_sum_i32(ne, S.red);
+    ne = block_sum_i32(ne, red);
     int nv = 0;   // votes that landed in a column (counted as each row enters the band)
     // initial band rows max(v_max - chi, v_h) .. v_max, four rows of loads in flight at a time
     for (int v = max(v_max - chi, v_h); v <= v_max; v += 4) {
@@ -958,13 +932,13 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
     // row-invariant per-thread constants: LDS positions of the window Sh(c0-5 .. c0+12) and
     // of the own columns in both DP buffers, and the slope offsets slope * c of the window
     constexpr int kWin = kDpRun + 10;
-    int posA[kWin], posB[kWin], offw[kWin];
+    // window column c0 - 5 + j sits at int index t + K[j] of a DP row (K uniform over the
+    // workgroup: K[j] = ((3 + j) mod 8) NR + (3 + j) div 8), and its slope offset is
+    // slope * c0 + slope * (j - 5)
+    int K[kWin];
 #pragma unroll
-    for (int j = 0; j < kWin; ++j) {
-        posA[j] = WP + ipos(c0 - 5 + j, NR);      // absolute int index of Sa (Sa = smem + WP)
-        posB[j] = posA[j] + WP;                    // Sb = Sa + WP
-        offw[j] = slope * (c0 - 5 + j);
-    }
+    for (int j = 0; j < kWin; ++j) K[j] = ((3 + j) & (kDpRun - 1)) * NR + ((3 + j) >> 3);
+    const int sc0 = slope * c0;
     const bool full5 = tau_max == 5;
     // band rows entering / leaving at the next DP row, prefetched one row ahead
     int nadd[kBandPer], nrem[kBandPer];
@@ -990,12 +964,15 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
         band_apply(crem, -1, hist, NR);
         __syncthreads();
         if (c0 < W2) {
+            const int* src = (parity ? Sb : Sa) + t;
+            int* dst = (parity ? Sa : Sb) + t;
             int w[kWin], TL[kWin], TR[kWin];
 #pragma unroll
             for (int j = 0; j < kWin; ++j) {
-                w[j] = smem_i(smem)[parity ? posB[j] : posA[j]];
-                TL[j] = w[j] - offw[j];          // key of tau < 0 minus the per-c constant
-                TR[j] = w[j] + offw[j];          // key of tau > 0 plus the per-c constant
+                w[j] = src[K[j]];
+                const int off = sc0 + slope * (j - 5);
+                TL[j] = w[j] - off;              // key of tau < 0 minus the per-c constant
+                TR[j] = w[j] + off;              // key of tau > 0 plus the per-c constant
             }
             uint32_t word = 0;
 #pragma unroll
@@ -1010,11 +987,10 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
                     for (int a = 1; a <= 5; ++a)
                         if (a <= tau_max) { lm = min(lm, TL[k + 5 - a]); rm = min(rm, TR[k + 5 + a]); }
                 }
-                const int cc = offw[k + 5];                          // slope * c
+                const int cc = sc0 + slope * k;                      // slope * c
                 const int key = min(w[k + 5], min(lm + (cc - 1), rm - cc));
-                const int posc = parity ? posA[k + 5] : posB[k + 5];   // destination buffer
                 if (c0 + k < W2) {
-                    smem_i(smem)[posc] = ((key >> 4) - hist[posA[k + 5] - WP]) * 16;
+                    dst[K[k + 5]] = ((key >> 4) - hist[t + K[k + 5]]) * 16;
                     word |= (uint32_t)(key & 15) << (4 * k);
                 }
             }
@@ -1051,8 +1027,6 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
             const int last = min(v0 + kWalkRows - 1, v_max);
             for (int v = v0; v <= last; ++v) {
                 d.mxpath[(int64_t)b * H + v] = cc;
-                PX[v - v_h] = v;
-                PY[v - v_h] = cc - d.half;
                 if (v < v_max) {
                     const uint32_t wd = win[(v - v0) * ww + cc / kDpRun - w0];
                     cc += rank_to_tau((int)((wd >> (4 * (cc % kDpRun))) & 15u));
@@ -1062,8 +1036,59 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d, const uint64_t* stream_
         }
         __syncthreads();
     }
-    vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx,
-                 seed_gamma ? seed_gamma + 5 * (int64_t)b : nullptr, vp_out, ne, nv);
+    nv = block_sum_i32(nv, red);
+    if (t == 0) {
+        fi.n_edges = ne;
+        fi.n_votes = nv;
+        d.info[b] = fi;
+    }
+}
+
+// S8 for every frame: RANSAC of the quartic through the row-DP path (read back from the path
+// columns), V_px and the track tables.  One 128-thread workgroup per frame (the RANSAC's
+// registers allow many per CU).  Hypothesis 0: the caller's seed rows (plain search), or the
+// seed of the narrowed search for the frames that kept it (pruned = 1).
+__global__ __launch_bounds__(128) void k_vpx_ransac(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+                                                    const double* seed_gamma, int pruned, double* vp_out) {
+    extern __shared__ unsigned char smem[];
+    __shared__ RansacShared S;
+    const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    if (frame_masked(d, b)) return;
+    const int H = d.H, v_max = H - 1;
+    const FrameInfo fi = d.info[b];
+    double* tf = d.tab + (int64_t)b * 6 * H;
+    for (int v = t; v < H; v += nt) {
+        tf[4 * H + v] = 0.0;
+        tf[5 * H + v] = 0.0;
+    }
+    if (fi.flags & LD_FLAG_NOROAD) {
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        if (vp_out)
+            for (int v = t; v < H; v += nt) {
+                vp_out[((int64_t)b * H + v) * 2] = nan;
+                vp_out[((int64_t)b * H + v) * 2 + 1] = nan;
+            }
+        return;
+    }
+    const int v_h = fi.v_h;
+    int* PX = reinterpret_cast<int*>(smem);
+    int* PY = PX + H;
+    int* cur = PY + H;
+    int* cur2 = cur + H;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cur2 + H);
+    const int bm_words = (H + 31) / 32;
+    for (int v = v_h + t; v <= v_max; v += nt) {
+        PX[v - v_h] = v;
+        PY[v - v_h] = d.mxpath[(int64_t)b * H + v] - d.half;
+    }
+    __syncthreads();
+    const double* seed = nullptr;
+    if (pruned) {
+        if (!(d.prune[(int64_t)b * kPruneWords + 1] & kFbPlainVpx)) seed = d.seedg + 5 * (int64_t)b;
+    } else if (seed_gamma) {
+        seed = seed_gamma + 5 * (int64_t)b;
+    }
+    vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx, seed, vp_out);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1410,12 +1435,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 // that the path never reaches an inner edge of the window, then the fit.  One workgroup of
 // 256 threads per frame (one window column each); the backtrace (int8 per row and window
 // column) uses the frame's backtrace buffer.
-__global__ __launch_bounds__(256, 4) void k_vpx_window(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
-                                                    double* vp_out) {
+__global__ __launch_bounds__(256) void k_vpx_window(Dev d) {
     extern __shared__ unsigned char smem[];
-    __shared__ RansacShared S;
     __shared__ int64_t rv[kMaxWaves];
     __shared__ int ri[kMaxWaves];
+    __shared__ int red[kMaxWaves];
     __shared__ int s_touch;
     const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
     if (frame_masked(d, b)) return;
@@ -1423,26 +1447,15 @@ __global__ __launch_bounds__(256, 4) void k_vpx_window(Dev d, const uint64_t* st
     if (pr[1] & kFbPlainVpx) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
     FrameInfo fi = d.info[b];
-    double* tf = d.tab + (int64_t)b * 6 * H;
-    for (int v = t; v < H; v += nt) {
-        tf[4 * H + v] = 0.0;
-        tf[5 * H + v] = 0.0;
-        d.mxpath[(int64_t)b * H + v] = -1;
-    }
-    const int v_h = fi.v_h, R = v_max - v_h + 1, chi = d.P.chi;
+    for (int v = t; v < H; v += nt) d.mxpath[(int64_t)b * H + v] = -1;
+    const int v_h = fi.v_h, chi = d.P.chi;
     const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
     // LDS: two delta rows of the band histogram (ping-pong by row), two DP rows with 5 guard
-    // columns of kBig on each side, the fit scratch
+    // columns of kBig on each side, the per-row edge counts
     int* dlt = reinterpret_cast<int*>(smem);    // 2 x 256
     int* Ea = dlt + 512;                         // 266
     int* Eb = Ea + 266;                          // 266
-    int* PX = Eb + 266;
-    int* PY = PX + H;
-    int* cur = PY + H;
-    int* cur2 = cur + H;
-    int* cntL = cur2 + H;
-    uint32_t* bitmap = reinterpret_cast<uint32_t*>(cntL + H);
-    const int bm_words = (H + 31) / 32;
+    int* cntL = Eb + 266;                        // H
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
     for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
     for (int i = t; i < 512; i += nt) dlt[i] = 0;
@@ -1450,7 +1463,7 @@ __global__ __launch_bounds__(256, 4) void k_vpx_window(Dev d, const uint64_t* st
     __syncthreads();
     int ne = 0;
     for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
-    ne = block_sum_i32(ne, S.red);
+    ne = block_sum_i32(ne, red);
     int nv = 0;
     // the initial band, then the column count of thread t's own window column lives in h
     for (int r = max(v_max - chi, v_h); r <= v_max; ++r) {
@@ -1540,17 +1553,17 @@ __global__ __launch_bounds__(256, 4) void k_vpx_window(Dev d, const uint64_t* st
         for (int v = v_h; v <= v_max; ++v) {
             if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
             d.mxpath[(int64_t)b * H + v] = lo + c;
-            PX[v - v_h] = v;
-            PY[v - v_h] = lo + c - d.half;
             if (v < v_max) c += back[(int64_t)(v - v_h) * win + c];
         }
         s_touch = touch;
         if (touch) pr[1] |= kFbPlainVpx | kFbTouch;
     }
-    __syncthreads();
-    if (s_touch) return;
-    vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx, d.seedg + (int64_t)b * 5,
-                 vp_out, ne, nv);
+    nv = block_sum_i32(nv, red);
+    if (t == 0 && !s_touch) {
+        fi.n_edges = ne;
+        fi.n_votes = nv;
+        d.info[b] = fi;
+    }
 }
 
 // Candidate mask: candidate i is kept when its track meets a marking pixel on a band row, then
@@ -1657,8 +1670,8 @@ __global__ void k_lane_check(Dev d, ld_lanes* lanes, int nframes, int pruning) {
 // ==========================================================================================
 // Host side: frame objects and the C ABI.
 // k_vdisp_hist, k_vdisp_fit, k_edges, k_vpx_fit, k_energy, k_peaks, then the pruned search:
-// k_cnn_fwd, k_seed, k_vpx_window, k_cand_mask + k_lane_check
-constexpr int kNumKernels = 10;
+// k_cnn_fwd, k_seed, k_vpx_window, k_cand_mask + k_lane_check, then k_vpx_ransac
+constexpr int kNumKernels = 11;
 
 struct ProfEvent {
     int kernel;
@@ -1735,7 +1748,7 @@ int vpx_fit_threads(const Dev& d) {
 
 size_t vpx_fit_lds(const Dev& d) {
     const size_t WP = (size_t)kDpRun * ((d.W2 + kDpRun - 1) / kDpRun + 2);
-    return sizeof(int) * (3 * WP + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32 + (size_t)vpx_walk_words_dev(d.W2));
+    return sizeof(int) * (3 * WP + (size_t)d.H) + sizeof(uint32_t) * (size_t)vpx_walk_words_dev(d.W2);
 }
 
 size_t energy_lds(const Dev& d) { return sizeof(float) * (3 * (size_t)d.W + 4); }
@@ -1843,26 +1856,37 @@ ld_status run_edges(ld_frame f, const uint8_t* grey, int64_t gp, const void* dis
     return launch_ok();
 }
 
-// the full V_px search of S6-S8 for the frames that `d` selects
-ld_status run_vpx(ld_frame f, const Dev& d, const uint64_t* sid, const int64_t* fidx, const double* seed_gamma,
-                  double* vp_out, hipStream_t st) {
+// the full band accumulator and row DP of S6-S7 for the frames that `d` selects
+ld_status run_vpx_dp(ld_frame f, const Dev& d, hipStream_t st) {
     const size_t l4 = vpx_fit_lds(d);
     const int nt4 = vpx_fit_threads(d);
     ProfScope ps(f, 3, st);
     if (nt4 <= 512) {
         allow_lds(k_vpx_fit<512>, l4);
-        hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
+        hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d);
     } else {
         allow_lds(k_vpx_fit<1024>, l4);
-        hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d, sid, fidx, seed_gamma, vp_out);
+        hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d);
     }
+    return launch_ok();
+}
+
+// S8 for every active frame
+ld_status run_vpx_ransac(ld_frame f, const uint64_t* sid, const int64_t* fidx, const double* seed_gamma, int pruned,
+                         double* vp_out, hipStream_t st) {
+    const Dev& d = f->d;
+    const size_t l = sizeof(int) * 4 * (size_t)d.H + sizeof(uint32_t) * ((d.H + 31) / 32);
+    allow_lds(k_vpx_ransac, l);
+    ProfScope ps(f, 10, st);
+    hipLaunchKernelGGL(k_vpx_ransac, dim3(f->active), dim3(128), l, st, d, sid, fidx, seed_gamma, pruned, vp_out);
     return launch_ok();
 }
 
 ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, const uint64_t* sid,
                  const int64_t* fidx, const double* seed_gamma, double* vp_out, hipStream_t st) {
     ld_status s = run_edges(f, grey, gp, disp, dpt, st);
-    if (s == LD_OK) s = run_vpx(f, f->d, sid, fidx, seed_gamma, vp_out, st);
+    if (s == LD_OK) s = run_vpx_dp(f, f->d, st);
+    if (s == LD_OK) s = run_vpx_ransac(f, sid, fidx, seed_gamma, 0, vp_out, st);
     return s;
 }
 
@@ -2109,16 +2133,17 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     }
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
-        const size_t lw = sizeof(int) * (512 + 2 * 266 + 5 * (size_t)d.H) + sizeof(uint32_t) * ((d.H + 31) / 32);
+        const size_t lw = sizeof(int) * (512 + 2 * 266 + (size_t)d.H);
         allow_lds(k_vpx_window, lw);
-        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(256), lw, st, d, stream_ids, frame_idx, nullptr);
+        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(256), lw, st, d);
         s = launch_ok();
     }
     Dev full = d;                       // frames sent back to the full V_px search
     full.only = d.prune;
     full.only_bits = kFbPlainVpx;
     full.only_set = 1;
-    if (s == LD_OK) s = run_vpx(f, full, stream_ids, frame_idx, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_vpx_dp(f, full, st);
+    if (s == LD_OK) s = run_vpx_ransac(f, stream_ids, frame_idx, nullptr, 1, nullptr, st);
     if (s == LD_OK) {
         ProfScope ps(f, 9, st);
         const size_t lm = sizeof(uint32_t) * nb * LDI_BAND_ROWS * (size_t)((d.W + 31) / 32) + (size_t)d.W2;

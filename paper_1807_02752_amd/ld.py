@@ -145,7 +145,7 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
             "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
-           "k_vpx_window", "k_cand_mask"]
+           "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
 
 def check(status: int, what: str = "ld call"):
