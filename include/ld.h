@@ -312,7 +312,8 @@ ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t g
  *     marking pixel; kept candidates are dilated by `dilate`;
  *  5. energies of the kept candidates (0 for the others) and peaks.
  * Fallback to the plain search (LD_FLAG_FALLBACK) for a frame: no seed (fewer than
- * min_votes marking votes), or the window path touches an inner window edge -> plain
+ * min_votes marking votes, or a frame narrower than 128 columns), or the window path
+ * touches an inner window edge -> plain
  * accumulator, DP and unseeded RANSAC; no lane, or a lane next to a pruned candidate ->
  * energies of every candidate and peaks again. */
 ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,

@@ -850,7 +850,7 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
         } else {
             lo = std::max(0, cs - L->delta_x);
             hi = std::min(W2 - 1, cs + L->delta_x);
-            if (hi - lo + 1 > W) fb = 1 | 4;
+            if (W < 128) fb = 1 | 4;     // frames narrower than 128 columns take the full search
         }
         int klo = -1, khi = -1;
         for (int k = 0; k < nb; ++k)

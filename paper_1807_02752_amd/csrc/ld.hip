@@ -1404,7 +1404,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
             cs = bi;
             lo = max(0, cs - delta);
             hi = min(W2 - 1, cs + delta);
-            if (hi - lo + 1 > W) fb = kFbPlainVpx | kFbNoSeed;   // the window buffer holds W columns per row
+            if (W < 128) fb = kFbPlainVpx | kFbNoSeed;   // the window backtrace needs 128 B per row
         }
         // hypothesis 0: line through the lowest and the highest band with min_votes votes
         int klo = -1, khi = -1;
@@ -1432,134 +1432,184 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 
 // Windowed V_px search: band accumulator and row DP on columns lo..hi only (transitions
 // leaving the window are not allowed), the same tie order as the full DP, backtrace, a check
-// that the path never reaches an inner edge of the window, then the fit.  One workgroup of
-// 256 threads per frame (one window column each); the backtrace (int8 per row and window
-// column) uses the frame's backtrace buffer.
-__global__ __launch_bounds__(256) void k_vpx_window(Dev d) {
+// that the path never reaches an inner edge of the window.  One wave per frame: lane l keeps
+// window columns 4l .. 4l+3 (E of the previous row and the column counts) in registers and
+// takes the neighbours' E from lanes l-2 .. l+2 by shuffles, so a row needs no barrier; the
+// band deltas of a row go through LDS atomics, from the road rows' vote columns staged in LDS
+// before the sweep; the backtrace (tau + 5, 4 bits per column,
+// 128 B per row) goes to the frame's backtrace buffer and is walked through LDS 32 rows at a
+// time.  Needs W >= 128 (the buffer holds W bytes per row); narrower frames use the full search.
+constexpr int kWalkChunk = 32;
+
+__device__ __forceinline__ int shfl_i(int x, int src) { return __shfl(x, src, kWave); }
+
+__global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
     extern __shared__ unsigned char smem[];
-    __shared__ int64_t rv[kMaxWaves];
-    __shared__ int ri[kMaxWaves];
-    __shared__ int red[kMaxWaves];
-    __shared__ int s_touch;
-    const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
+    const int b = blockIdx.x, l = lane_id();
     if (frame_masked(d, b)) return;
     int32_t* pr = d.prune + (int64_t)b * kPruneWords;
     if (pr[1] & kFbPlainVpx) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
     FrameInfo fi = d.info[b];
-    for (int v = t; v < H; v += nt) d.mxpath[(int64_t)b * H + v] = -1;
-    const int v_h = fi.v_h, chi = d.P.chi;
+    for (int v = l; v < H; v += kWave) d.mxpath[(int64_t)b * H + v] = -1;
+    const int v_h = fi.v_h, chi = d.P.chi, R = v_max - v_h + 1;
     const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
-    // LDS: two delta rows of the band histogram (ping-pong by row), two DP rows with 5 guard
-    // columns of kBig on each side, the per-row edge counts
-    int* dlt = reinterpret_cast<int*>(smem);    // 2 x 256
-    int* Ea = dlt + 512;                         // 266
-    int* Eb = Ea + 266;                          // 266
-    int* cntL = Eb + 266;                        // H
+    int* dlt = reinterpret_cast<int*>(smem);                 // 256 band deltas of a row
+    int* cntL = dlt + 256;                                    // H
+    int* path = cntL + H;                                     // H + 1 (the last: touch flag)
+    int* roff = path + H + 1;                                 // R + 1 <= H + 1
+    uint16_t* stage = reinterpret_cast<uint16_t*>(roff + H + 1);          // kWalkChunk x 64
+    uint8_t* wb = reinterpret_cast<uint8_t*>(stage + kWave * kWalkChunk);  // stage_cap bytes
+    uint16_t* back = reinterpret_cast<uint16_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 2;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
-    for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
-    for (int i = t; i < 512; i += nt) dlt[i] = 0;
-    for (int i = t; i < 266; i += nt) { Ea[i] = kBig; Eb[i] = kBig; }
-    __syncthreads();
-    int ne = 0;
-    for (int v = v_h + t; v <= v_max; v += nt) ne += cntL[v];
-    ne = block_sum_i32(ne, red);
+    for (int v = l; v < H; v += kWave) cntL[v] = d.rowcnt[(int64_t)b * H + v];
+    for (int i = l; i < 256; i += kWave) dlt[i] = 0;
+    {   // exclusive prefix of the road rows' edge counts, 64 rows per wave scan
+        int carry = 0;
+        for (int base = 0; base < R; base += kWave) {
+            const int own = base + l < R ? d.rowcnt[(int64_t)b * H + v_h + base + l] : 0;
+            int x = own;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(x, o, kWave);
+                if (l >= o) x += y;
+            }
+            if (base + l < R) roff[base + l] = carry + x - own;
+            carry += __shfl(x, kWave - 1, kWave);
+        }
+        if (l == 0) roff[R] = carry;
+    }
+    const int ne = roff[R];
+    // window offset of every road edge's vote column (255: outside the window or no vote),
+    // loaded eight rows at a time with every load of the group in flight
+    const bool staged = ne <= stage_cap;
+    auto woff = [&](int c) -> uint8_t { return (c >= lo && c <= hi) ? (uint8_t)(c - lo) : (uint8_t)255; };
     int nv = 0;
-    // the initial band, then the column count of thread t's own window column lives in h
-    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) {
+    if (staged) {
+        for (int v0 = v_h; v0 <= v_max; v0 += 16) {
+            int c2[16][2];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int v = v0 + k, n = v <= v_max ? cntL[v] : 0;
+                c2[k][0] = l < n ? fe[(int64_t)v * d.W + l].bin : -1;
+                c2[k][1] = l + kWave < n ? fe[(int64_t)v * d.W + l + kWave].bin : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int v = v0 + k;
+                if (v > v_max) break;
+                const int n = cntL[v], o = roff[v - v_h];
+                nv += (c2[k][0] >= 0 ? 1 : 0) + (c2[k][1] >= 0 ? 1 : 0);
+                if (l < n) wb[o + l] = woff(c2[k][0]);
+                if (l + kWave < n) wb[o + l + kWave] = woff(c2[k][1]);
+                for (int i = l + 2 * kWave; i < n; i += kWave) {
+                    const int c = fe[(int64_t)v * d.W + i].bin;
+                    nv += c >= 0 ? 1 : 0;
+                    wb[o + i] = woff(c);
+                }
+            }
+        }
+    } else {
+        for (int v = v_h; v <= v_max; ++v)
+            for (int i = l; i < cntL[v]; i += kWave) nv += fe[(int64_t)v * d.W + i].bin >= 0 ? 1 : 0;
+    }
+    // band rows entering (sign +1) or leaving (-1) the accumulator
+    auto apply = [&](int r, int sign) {
         const int n = cntL[r];
-        for (int i = t; i < n; i += nt) {
-            const int c = fe[(int64_t)r * d.W + i].bin;
-            nv += c >= 0 ? 1 : 0;
-            if (c >= lo && c <= hi) atomicAdd(&dlt[c - lo], 1);
+        const int o = staged ? roff[r - v_h] : 0;
+        for (int base = 0; base < n; base += kWave) {
+            const int i = base + l;
+            int key = -1;
+            if (i < n) {
+                if (staged) {
+                    const int c = wb[o + i];
+                    key = c != 255 ? c : -1;
+                } else {
+                    const int c = fe[(int64_t)r * d.W + i].bin;
+                    key = (c >= lo && c <= hi) ? c - lo : -1;
+                }
+            }
+            if (key >= 0) atomicAdd(&dlt[key], sign);
         }
+    };
+    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1);
+    int h[4], E[4];
+    {
+        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
+        h[0] = q.x; h[1] = q.y; h[2] = q.z; h[3] = q.w;
+        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
     }
-    __syncthreads();
-    int h = 0;
-    if (t < win) { h = dlt[t]; dlt[t] = 0; Ea[5 + t] = -h; }
-    __syncthreads();
-    // vote columns of the rows entering (v - chi) and leaving (v + chi + 1) at DP row v, two
-    // per thread, loaded kAhead rows ahead into a register ring; rows with more than 2 nt
-    // edges finish in a loop
-    constexpr int kAhead = 2;
-    auto load2 = [&](int r, bool ok, int* c2) {
-        const int n = ok ? cntL[r] : 0;
-        c2[0] = t < n ? fe[(int64_t)r * d.W + t].bin : -1;
-        c2[1] = t + nt < n ? fe[(int64_t)r * d.W + t + nt].bin : -1;
-    };
-    auto load_row = [&](int v, int* a2, int* r2) {   // the bins DP row v needs (none beyond v_h)
-        const int ra = v - chi, rr = v + chi + 1;
-        load2(max(ra, 0), v >= v_h && ra >= v_h, a2);
-        load2(min(rr, v_max), v >= v_h && rr <= v_max, r2);
-    };
-    int na[kAhead][2], nr[kAhead][2];
 #pragma unroll
-    for (int k = 0; k < kAhead; ++k) load_row(v_max - 1 - k, na[k], nr[k]);
+    for (int j = 0; j < 4; ++j) E[j] = 4 * l + j < win ? -h[j] : kBig;
     const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
-    int8_t* back = reinterpret_cast<int8_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 4;
-    int* E = Ea;
-    int* En = Eb;
     for (int v = v_max - 1; v >= v_h; --v) {
-        int* D = dlt + (v & 1) * 256;
-        const int ra = v - chi, rr = v + chi + 1;
-        int ca[2], cr[2];
+        if (v - chi >= v_h) apply(v - chi, 1);
+        if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
+        // the wave's LDS operations complete in order: the deltas are final here
+        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
+        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
+        h[0] += q.x; h[1] += q.y; h[2] += q.z; h[3] += q.w;
+        // E of columns 4l-8 .. 4l+11 of the previous row (kBig outside the window)
+        int nb[20];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) { ca[k] = na[0][k]; cr[k] = nr[0][k]; }
-#pragma unroll
-        for (int j = 0; j + 1 < kAhead; ++j)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) { na[j][k] = na[j + 1][k]; nr[j][k] = nr[j + 1][k]; }
-        load_row(v - kAhead, na[kAhead - 1], nr[kAhead - 1]);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            nv += ca[k] >= 0 ? 1 : 0;
-            if (ca[k] >= lo && ca[k] <= hi) atomicAdd(&D[ca[k] - lo], 1);
-            if (cr[k] >= lo && cr[k] <= hi) atomicAdd(&D[cr[k] - lo], -1);
+        for (int j = 0; j < 4; ++j) {
+            const int a = shfl_i(E[j], l - 2), bb = shfl_i(E[j], l - 1), c = shfl_i(E[j], l + 1), e2 = shfl_i(E[j], l + 2);
+            nb[j] = l >= 2 ? a : kBig;
+            nb[4 + j] = l >= 1 ? bb : kBig;
+            nb[8 + j] = E[j];
+            nb[12 + j] = l + 1 < kWave ? c : kBig;
+            nb[16 + j] = l + 2 < kWave ? e2 : kBig;
         }
-        if (ra >= v_h)
-            for (int i = t + 2 * nt; i < cntL[ra]; i += nt) {
-                const int c = fe[(int64_t)ra * d.W + i].bin;
-                nv += c >= 0 ? 1 : 0;
-                if (c >= lo && c <= hi) atomicAdd(&D[c - lo], 1);
+        uint32_t bits = 0;
+        int En[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int best = nb[8 + j], bt = 0;
+#pragma unroll
+            for (int a = 1; a <= 5; ++a) {
+                if (a > tau_max) break;
+                const int left = nb[8 + j - a] + lam * a, right = nb[8 + j + a] + lam * a;
+                if (left < best) { best = left; bt = -a; }
+                if (right < best) { best = right; bt = a; }
             }
-        if (rr <= v_max)
-            for (int i = t + 2 * nt; i < cntL[rr]; i += nt) {
-                const int c = fe[(int64_t)rr * d.W + i].bin;
-                if (c >= lo && c <= hi) atomicAdd(&D[c - lo], -1);
-            }
-        __syncthreads();
-        if (t < win) {
-            h += D[t];
-            D[t] = 0;
-            const int* e = E + 5 + t;
-            int best = e[0], bt = 0;
-            for (int a = 1; a <= tau_max; ++a) {
-                const int l = e[-a] + lam * a, r = e[a] + lam * a;
-                if (l < best) { best = l; bt = -a; }
-                if (r < best) { best = r; bt = a; }
-            }
-            En[5 + t] = -h + best;
-            back[(int64_t)(v - v_h) * win + t] = (int8_t)bt;
+            En[j] = 4 * l + j < win ? -h[j] + best : kBig;
+            bits |= (uint32_t)(bt + 5) << (4 * j);
         }
-        int* tmp = E; E = En; En = tmp;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) E[j] = En[j];
+        back[(int64_t)(v - v_h) * kWave + l] = (uint16_t)bits;
     }
-    __syncthreads();
+    // start column: argmin over the window of E at v_h, ties to the smaller column
     int64_t bv = INT64_MAX;
     int bc = 0x7fffffff;
-    if (t < win) { bv = E[5 + t]; bc = t; }
-    block_argmin_i64(bv, bc, rv, ri);
-    if (t == 0) {
-        int c = bc, touch = 0;
-        for (int v = v_h; v <= v_max; ++v) {
-            if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
-            d.mxpath[(int64_t)b * H + v] = lo + c;
-            if (v < v_max) c += back[(int64_t)(v - v_h) * win + c];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (4 * l + j < win && (int64_t)E[j] < bv) { bv = E[j]; bc = 4 * l + j; }
+    wave_argmin_i64(bv, bc);
+    __threadfence_block();   // the backtrace stores are complete before the wave reads them back
+    int c = bc, touch = 0;
+    for (int v0 = v_h; v0 <= v_max; v0 += kWalkChunk) {
+        const int rows = min(kWalkChunk, v_max - v0);          // rows with a backtrace entry
+        for (int r = 0; r < rows; ++r) stage[r * kWave + l] = back[(int64_t)(v0 - v_h + r) * kWave + l];
+        if (l == 0) {
+            const int last = min(v0 + kWalkChunk - 1, v_max);
+            for (int v = v0; v <= last; ++v) {
+                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
+                path[v] = lo + c;
+                if (v < v_max) c += (int)((stage[(v - v0) * kWave + (c >> 2)] >> (4 * (c & 3))) & 15u) - 5;
+            }
+            path[H] = touch;
         }
-        s_touch = touch;
-        if (touch) pr[1] |= kFbPlainVpx | kFbTouch;
+        c = __shfl(c, 0, kWave);
     }
-    nv = block_sum_i32(nv, red);
-    if (t == 0 && !s_touch) {
+    nv = wave_sum_i32(nv);
+    touch = path[H];
+    if (touch) {
+        if (l == 0) pr[1] |= kFbPlainVpx | kFbTouch;
+        return;
+    }
+    for (int v = v_h + l; v <= v_max; v += kWave) d.mxpath[(int64_t)b * H + v] = path[v];
+    if (l == 0) {
         fi.n_edges = ne;
         fi.n_votes = nv;
         d.info[b] = fi;
@@ -2133,9 +2183,10 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     }
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
-        const size_t lw = sizeof(int) * (512 + 2 * 266 + (size_t)d.H);
+        const int cap = std::min(32768, std::max(4096, 16 * d.W));   // staged road edges (bytes)
+        const size_t lw = sizeof(int) * (256 + 3 * (size_t)d.H + 2) + sizeof(uint16_t) * kWave * kWalkChunk + cap;
         allow_lds(k_vpx_window, lw);
-        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(256), lw, st, d);
+        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(kWave), lw, st, d, cap);
         s = launch_ok();
     }
     Dev full = d;                       // frames sent back to the full V_px search
