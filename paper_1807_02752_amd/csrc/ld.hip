@@ -362,52 +362,73 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
 // frame into LDS; within a wave, the lanes that share the first active lane's bin are merged
 // by ballot into one LDS atomic and the other lanes add directly (a road row puts most
 // pixels into one or two bins, so one merge removes most of the same-address traffic).  Rows
-// are loaded four at a time (every load of the four rows in flight), and the counts leave
-// transposed, hist_rows consecutive rows per disparity.
+// are taken four at a time, and the raw values of the next four rows are loaded while the
+// current four are binned, so a wave always has a group of loads in flight.  The counts
+// leave transposed, hist_rows consecutive rows per disparity.
 constexpr int kHistGroup = 4;
 
+template <int FMT> struct RawPixel { using T = uint8_t; };
+template <> struct RawPixel<LD_DISP_F32> { using T = float; };
+template <> struct RawPixel<LD_DISP_U16Q4> { using T = uint16_t; };
+
+// Bin of one raw disparity value; false for the invalid ones (0 in the integer formats,
+// non-positive or non-finite in F32), so a load masked to 0 is never counted.
 template <int FMT>
-__device__ __forceinline__ bool disp_bin(const uint8_t* row, int u, int d_max, int& bin) {
+__device__ __forceinline__ bool disp_bin(typename RawPixel<FMT>::T x, int d_max, int& bin) {
     if (FMT == LD_DISP_U8) {
-        int r = row[u];
-        bin = min(r, d_max);
-        return r != 0;
+        bin = min((int)x, d_max);
+        return x != 0;
     } else if (FMT == LD_DISP_F32) {
-        float x = reinterpret_cast<const float*>(row)[u];
-        if (!(isfinite(x) && x > 0.0f)) return false;
+        if (!(isfinite((float)x) && (float)x > 0.0f)) return false;
         double b = floor((double)x + 0.5);
         bin = b > (double)d_max ? d_max : (int)b;
         return true;
     } else {
-        int r = reinterpret_cast<const uint16_t*>(row)[u];
-        bin = min((r + 8) >> 4, d_max);
-        return r != 0;
+        bin = min(((int)x + 8) >> 4, d_max);
+        return x != 0;
+    }
+}
+
+template <int FMT, int NPT>
+__device__ __forceinline__ void hist_load(const typename RawPixel<FMT>::T* base, int64_t pitch_px, int W, int t,
+                                          int g, int rows, typename RawPixel<FMT>::T (&dst)[kHistGroup][NPT]) {
+#pragma unroll
+    for (int r = 0; r < kHistGroup; ++r) {
+        const typename RawPixel<FMT>::T* row = base + (int64_t)min(g + r, rows - 1) * pitch_px;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int u = t + k * kBlock;
+            dst[r][k] = (g + r < rows && u < W) ? row[u] : typename RawPixel<FMT>::T(0);
+        }
     }
 }
 
 template <int FMT, int NPT>
 __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* disp, int64_t pitch, int32_t* vdisp_out) {
+    using Raw = typename RawPixel<FMT>::T;
     extern __shared__ int hist[];   // hist_rows x D1
     const int hr = d.hist_rows;
     const int b = blockIdx.y, v0 = blockIdx.x * hr, t = threadIdx.x, lane = lane_id();
     if (frame_masked(d, b)) return;
     const int D1 = d.D1, W = d.W, H = d.H;
     const int rows = min(hr, H - v0);
+    const Raw* base = reinterpret_cast<const Raw*>(disp + ((int64_t)b * H + v0) * pitch);
+    const int64_t pitch_px = pitch / (int64_t)sizeof(Raw);
+    Raw nxt[kHistGroup][NPT];
+    hist_load<FMT, NPT>(base, pitch_px, W, t, 0, rows, nxt);
     for (int i = t; i < hr * D1; i += kBlock) hist[i] = 0;
     __syncthreads();
     for (int g = 0; g < rows; g += kHistGroup) {
         int bins[kHistGroup][NPT];
         bool ok[kHistGroup][NPT];
 #pragma unroll
-        for (int r = 0; r < kHistGroup; ++r) {
-            const uint8_t* row = disp + ((int64_t)b * H + v0 + g + r) * pitch;
+        for (int r = 0; r < kHistGroup; ++r)
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
-                const int u = t + k * kBlock;
                 bins[r][k] = 0;
-                ok[r][k] = (g + r < rows) && (u < W) && disp_bin<FMT>(row, u, d.d_max, bins[r][k]);
+                ok[r][k] = disp_bin<FMT>(nxt[r][k], d.d_max, bins[r][k]);
             }
-        }
+        if (g + kHistGroup < rows) hist_load<FMT, NPT>(base, pitch_px, W, t, g + kHistGroup, rows, nxt);
 #pragma unroll
         for (int r = 0; r < kHistGroup; ++r) {
 #pragma unroll
@@ -676,6 +697,9 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 // down its columns, loading one new row per step, with the next row's raw disparities in
 // flight.  The road test is an integer compare against the row's raw interval.  A row's
 // edges are appended to its bucket with one atomic per wave.
+// Pixels outside the frame are never read for a result: the gradient is taken only at
+// 1 <= u <= W-2 and 1 <= v <= H-2, so the loads clamp their row and column into the frame
+// instead of masking (lanes whose six columns are all inside take the branch-free path).
 constexpr int kEdgeRows = 16;
 constexpr int kQT = 64;                 // threads per workgroup (one wave), 4 columns each
 template <int FMT>
@@ -684,6 +708,29 @@ __device__ __forceinline__ uint32_t disp_raw(const uint8_t* row, int u) {
     if (FMT == LD_DISP_F32) return reinterpret_cast<const uint32_t*>(row)[u];
     return reinterpret_cast<const uint16_t*>(row)[u];
 }
+
+// Vote column of an edge: floor(x + 0.5) with x = u + (tt * gy) / gx in IEEE FP64, each
+// operation rounded as written.  The quotient is first taken as p * (1/gx) with the
+// reciprocal refined by two Newton steps and one residual correction, which is within an ulp
+// or two of the rounded quotient; the floor of x + 0.5 can differ from the exact one only
+// when x + 0.5 lies within a few ulps of an integer, and there (and for non-finite values)
+// the rounded division is taken.  Returns the bin or -1 when the column is outside
+// [-half, W2 - half).
+__device__ __forceinline__ int vote_bin(double tt, int gy, int gx, int u, int half, int W2) {
+    const double p = tt * (double)gy;
+    const double g = (double)gx;
+    double r = __builtin_amdgcn_rcp(g);
+    r = fma(r, fma(-g, r, 1.0), r);
+    r = fma(r, fma(-g, r, 1.0), r);
+    double q = p * r;
+    q = fma(fma(-g, q, p), r, q);
+    double y = ((double)u + q) + 0.5;
+    double bf = floor(y);
+    const double fr = y - bf;
+    if (!(fr >= 0x1p-30 && fr <= 1.0 - 0x1p-30)) bf = floor(((double)u + p / g) + 0.5);
+    return (bf >= -(double)half && bf < (double)(W2 - half)) ? (int)bf + half : -1;
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
                                                int64_t dpitch) {
@@ -698,13 +745,17 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
     const double* tvpy = d.tab + (int64_t)b * 6 * H + 2 * H;
     const uint32_t* rb = d.rbound + (int64_t)b * H * 2;
     const int t2 = d.P.edge_t * d.P.edge_t;
-    auto load_row = [&](int v, int* x) {     // x[0] = column ub-1 .. x[5] = ub+4, zero outside
-        const bool rok = v >= 0 && v < H;
-        const uint8_t* g = grey + ((int64_t)b * H + (rok ? v : 0)) * gpitch;
+    const bool inner = ub >= 1 && ub + 4 <= W - 1;
+    const uint8_t* gbase = grey + (int64_t)b * H * gpitch;
+    const uint8_t* dbase = disp + (int64_t)b * H * dpitch;
+    auto load_row = [&](int v, int* x) {     // x[0] = column ub-1 .. x[5] = ub+4
+        const uint8_t* g = gbase + (int64_t)min(max(v, 0), H - 1) * gpitch;
+        if (inner) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int u = ub - 1 + k;
-            x[k] = (rok && u >= 0 && u < W) ? (int)g[u] : 0;
+            for (int k = 0; k < 6; ++k) x[k] = g[ub - 1 + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) x[k] = g[min(max(ub - 1 + k, 0), W - 1)];
         }
     };
     int xa[6], xm[6], xc[6];
@@ -712,9 +763,14 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
     load_row(vs, xm);
     uint32_t rc[4], rn[4];
     auto load_raw = [&](int v, uint32_t* r) {
-        const uint8_t* dr = disp + ((int64_t)b * H + (v <= ve ? v : vs)) * dpitch;
+        const uint8_t* dr = dbase + (int64_t)min(v, ve) * dpitch;
+        if (inner) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = (v <= ve && ub + k < W) ? disp_raw<FMT>(dr, ub + k) : 0u;
+            for (int k = 0; k < 4; ++k) r[k] = disp_raw<FMT>(dr, ub + k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[k] = disp_raw<FMT>(dr, min(ub + k, W - 1));
+        }
     };
     load_raw(vs, rc);
     for (int v = vs; v <= ve; ++v) {
@@ -722,6 +778,7 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
         load_raw(v + 1, rn);
         const bool vin = v >= 1 && v <= H - 2;
         const uint32_t lo = rb[2 * v], hi = rb[2 * v + 1];
+        const double tt = (double)v - tvpy[v];
         uint32_t rec[4];
         int binv[4];
         uint64_t bal[4];
@@ -735,13 +792,8 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
                 gx = (xa[k + 2] - xa[k]) + 2 * (xm[k + 2] - xm[k]) + (xc[k + 2] - xc[k]);
                 gy = (xc[k] - xa[k]) + 2 * (xc[k + 1] - xa[k + 1]) + (xc[k + 2] - xa[k + 2]);
                 edge = gx * gx + gy * gy > t2;
-                if (edge && gx != 0) {
-                    const double tt = (double)v - tvpy[v];
-                    const double x = (double)u + (tt * (double)gy) / (double)gx;
-                    const double bf = floor(x + 0.5);
-                    if (bf >= -(double)d.half && bf < (double)(d.W2 - d.half)) bin = (int)bf + d.half;
-                }
             }
+            if (edge && gx != 0) bin = vote_bin(tt, gy, gx, u, d.half, d.W2);
             rec[k] = ((uint32_t)gx & 0xffffu) | ((uint32_t)gy << 16);
             binv[k] = bin;
             emask |= edge ? (1u << k) : 0u;
