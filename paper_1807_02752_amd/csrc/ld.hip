@@ -20,6 +20,7 @@
 #include <cstring>
 #include <new>
 #include <vector>
+#include <type_traits>
 
 #include "ld_device.h"
 #include "ld_internal.h"
@@ -1152,8 +1153,11 @@ __global__ __launch_bounds__(128) void k_vpx_ransac(Dev d, const uint64_t* strea
 // per-edge buffer.  Then the road rows are swept upwards: q row v-4 is scattered into a zeroed
 // LDS row, every thread pushes its NC columns into a 9-row register ring (rows v-4..v+4) and
 // forms V(x, v) = sum_y s_y C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0
-// outside the image; a candidate reads M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx)
-// (terms outside the image dropped) at its track column.  Two barriers per row.
+// outside the image; after a barrier the column owners form the row of
+// M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) (terms outside the image dropped) in one
+// of two LDS rows, and every candidate adds M_1 at its track column one row later, so a row
+// costs two barriers.  The row loop is unrolled nine times so that the ring rotates by
+// renaming registers instead of moving them.
 __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
     const double tx = (double)(-ed.gy), ty = (double)ed.gx;
     const double rx = vx - (double)ed.u, ry = vy - (double)r;
@@ -1167,6 +1171,8 @@ __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, dou
     const float w = sq ? expf(-(p * p) * inv_sg2) : expf(-p * inv_sg2);
     return (float)ed.gx * w;
 }
+
+template <int N> using IntC = std::integral_constant<int, N>;
 
 template <int NC, int NT>
 __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_mask, float* energy_out) {
@@ -1186,6 +1192,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     float* qb0 = fsm;                // W, dense q row (ping)
     float* qb1 = qb0 + W;            // W, dense q row (pong)
     float* Vp = qb1 + W;             // W + 4: V row with two zero columns on each side
+    float* mb0 = Vp + W + 4;         // W, M_1 row of even v
+    float* mb1 = mb0 + W;            // W, M_1 row of odd v
     const double* tf = d.tab + (int64_t)b * 6 * H;
     const double* tvpy = tf + 2 * H;
     const double* tvpx = tf + 3 * H;
@@ -1204,7 +1212,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         const double vx = tvpx[r], vy = tvpy[r];
         for (int i = lane; i < cnt; i += kWave) qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx, vy, inv_sg2, sq);
     }
-    for (int i = t; i < 3 * W + 4; i += kBlock) fsm[i] = 0.0f;
+    for (int i = t; i < 5 * W + 4; i += kBlock) fsm[i] = 0.0f;
     float ring[NC][9];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
@@ -1219,6 +1227,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         ee[k] = 0.0;
         live[k] = i < W2 && (cand_mask == nullptr || cand_mask[(int64_t)b * W2 + i] != 0);
     }
+    const double Wd = (double)W;
     __syncthreads();
 
     auto scatter = [&](int r, float* qb) {
@@ -1227,36 +1236,51 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
             for (int i = t; i < cnt; i += kBlock) qb[edges[(int64_t)r * W + i].u] = qbuf[(int64_t)r * W + i];
         }
     };
-    auto push = [&](float* qb) {   // slot 0 = newest row; reads and re-zeroes the owned columns
+    // slot S of the ring takes the newest row; reads and re-zeroes the owned columns of qb
+    auto push = [&](auto Sc, float* qb) {
+        constexpr int S = decltype(Sc)::value;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
-#pragma unroll
-            for (int j = 8; j > 0; --j) ring[k][j] = ring[k][j - 1];
-            ring[k][0] = 0.0f;
-            if (u < W) { ring[k][0] = qb[u]; qb[u] = 0.0f; }
+            ring[k][S] = 0.0f;
+            if (u < W) { ring[k][S] = qb[u]; qb[u] = 0.0f; }
         }
     };
-    int p = 0;
-    for (int r = v_max; r >= v_max - 3; --r) {     // rows below the image are zero
-        float* qb = p ? qb1 : qb0;
-        scatter(r, qb);
-        __syncthreads();
-        push(qb);
-        p ^= 1;
-    }
-    for (int v = v_max; v >= v_end; --v) {
-        float* qb = p ? qb1 : qb0;
+    // the track of every live candidate moves to row w and adds M_1(col, w)
+    auto candidates = [&](int w, const float* m1row) {
+        const bool upd = w < v_max;
+        const double A = upd ? tA[w] : 0.0, Bc = upd ? tB[w] : 1.0;   // fma(1, u, 0) = u
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            uu[k] = fma(Bc, uu[k], A);
+            const double x = uu[k] + 0.5;
+            const bool in = live[k] && x >= 0.0 && x < Wd;
+            const int col = in ? (int)floor(x) : 0;
+            const float m = m1row[col];
+            ee[k] += in ? (double)m : 0.0;    // ee is never -0, so adding +0 leaves it unchanged
+        }
+    };
+    // rows v_max .. v_max-3 enter slots 0, 8, 7, 6; rows below the image stay zero
+    scatter(v_max, qb0);     __syncthreads(); push(IntC<0>{}, qb0);
+    scatter(v_max - 1, qb1); __syncthreads(); push(IntC<8>{}, qb1);
+    scatter(v_max - 2, qb0); __syncthreads(); push(IntC<7>{}, qb0);
+    scatter(v_max - 3, qb1); __syncthreads(); push(IntC<6>{}, qb1);
+    int v = v_max;
+    // one row: newest ring slot S holds row v-4, slot (S + j) % 9 row v-4+j
+    auto step = [&](auto Sc) -> bool {
+        constexpr int S = decltype(Sc)::value;
+        if (v < v_end) return false;
+        float* qb = ((v_max - v) & 1) ? qb1 : qb0;
         scatter(v - 4, qb);
         __syncthreads();
-        push(qb);
-        p ^= 1;
-        // the ring holds q rows v-4 (slot 0) .. v+4 (slot 8)
+        push(Sc, qb);
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
             if (u < W) {
-                const float* r = ring[k];
+                float r[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
                 const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
                 const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
                 const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
@@ -1268,21 +1292,27 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
             }
         }
         __syncthreads();
-        const double A = v < v_max ? tA[v] : 0.0, Bc = v < v_max ? tB[v] : 0.0;
+        float* mrow = (v & 1) ? mb1 : mb0;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (live[k]) {
-                if (v < v_max) uu[k] = fma(Bc, uu[k], A);
-                const double x = uu[k] + 0.5;
-                if (x >= 0.0 && x < (double)W) {
-                    const int col = (int)floor(x);
-                    float m1 = 0.0f;
-                    if (col + 1 <= W - 1) m1 += (Vp[col + 2] + Vp[col + 3]) + Vp[col + 4];
-                    if (col >= 1) m1 -= (Vp[col] + Vp[col + 1]) + Vp[col + 2];
-                    ee[k] += (double)m1;
-                }
+        for (int k = 0; k < NC; ++k) {
+            const int u = t + k * kBlock;
+            if (u < W) {
+                float m1 = 0.0f;
+                if (u + 1 <= W - 1) m1 += (Vp[u + 2] + Vp[u + 3]) + Vp[u + 4];
+                if (u >= 1) m1 -= (Vp[u] + Vp[u + 1]) + Vp[u + 2];
+                mrow[u] = m1;
             }
         }
+        if (v < v_max) candidates(v + 1, ((v + 1) & 1) ? mb1 : mb0);
+        --v;
+        return true;
+    };
+    while (step(IntC<5>{}) && step(IntC<4>{}) && step(IntC<3>{}) && step(IntC<2>{}) && step(IntC<1>{}) &&
+           step(IntC<0>{}) && step(IntC<8>{}) && step(IntC<7>{}) && step(IntC<6>{})) {
+    }
+    if (v_end <= v_max) {
+        __syncthreads();
+        candidates(v_end, (v_end & 1) ? mb1 : mb0);
     }
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -1853,7 +1883,7 @@ size_t vpx_fit_lds(const Dev& d) {
     return sizeof(int) * (3 * WP + (size_t)d.H) + sizeof(uint32_t) * (size_t)vpx_walk_words_dev(d.W2);
 }
 
-size_t energy_lds(const Dev& d) { return sizeof(float) * (3 * (size_t)d.W + 4); }
+size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 4); }
 
 // Raise a kernel's dynamic LDS limit once per size (later launches, including those recorded
 // into a captured graph, issue nothing but the launch).
