@@ -38,7 +38,7 @@ constexpr int kCT = 60;              // output columns owned by a workgroup
 constexpr int kXW = 72;              // LDS columns, u = u0 - 4 + x
 constexpr int kLR = kBR + 2;         // LDS rows
 constexpr int kT = 256;              // threads per workgroup (4 waves)
-constexpr int kChunks = 18;          // packed A operands: 2 + 5 + 5 forward, 1 + 5 input gradient
+constexpr int kChunks = 28;          // packed A operands: 2 + 5 + 5 forward, 1 + 5 input gradient, 5 + 5 row sweep
 constexpr int kFeatElems = kLR * kXW * 4;
 constexpr int kActElems = kLR * kXW * 16;
 
@@ -51,6 +51,13 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {   // round to nearest e
     return u >> 16;
 }
 __device__ __forceinline__ float bf16_val(uint32_t h) { return __uint_as_float(h << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// bf16_bits(lo) | bf16_bits(hi) << 16 by the packed hardware conversion (also round to nearest even)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
 __device__ __forceinline__ float bf16_round(float f) { return bf16_val(bf16_bits(f)); }
 // the low 16 bits hold a BF16 value > 0 (ReLU outputs are >= 0 or -0)
 __device__ __forceinline__ bool positive(uint32_t h) { return (h & 0x7FFFu) != 0u && (h & 0x8000u) == 0u; }
@@ -88,6 +95,56 @@ constexpr int kGW = 72;              // staged grey columns u0-4 .. u0+67
 constexpr int kDW = 66;              // staged disparity columns u0-3 .. u0+62
 constexpr size_t kStageBytes = 18 * kGW + sizeof(float) * kBR * kDW + sizeof(double) * kBR;
 
+// Features of the staged tile (grey rows top-1 .. top+16, columns u0-4 .. u0+67; disparities
+// of rows top .. top+15, columns u0-3 .. u0+62; f(v) of the 16 rows) into feat at x = 1 .. 66
+// of rows 1 .. 16; pixels outside the frame get zero features.
+__device__ void features_from_stage(const ldi_frame_view& V, int u0, uint16_t* feat, const unsigned char* stage) {
+    const int W = V.W, t = threadIdx.x;
+    const uint8_t* gs = stage;
+    const float* ds = reinterpret_cast<const float*>(stage + 18 * kGW);
+    const double* fs = reinterpret_cast<const double*>(ds + kBR * kDW);
+    const float inv_pi = (float)(1.0 / 3.14159265358979323846);
+    for (int i = t; i < kBR * 66; i += kT) {
+        const int r = i / 66, x = 1 + i % 66, u = u0 - 4 + x;
+        uint2 pk = make_uint2(0u, 0u);
+        if (u >= 0 && u < W) {
+            const uint8_t* g0 = gs + r * kGW + x;          // row v-1, column u
+            const uint8_t* g1 = g0 + kGW;
+            const uint8_t* g2 = g1 + kGW;
+            const int gx = ((int)g0[1] - (int)g0[-1]) + 2 * ((int)g1[1] - (int)g1[-1]) + ((int)g2[1] - (int)g2[-1]);
+            const int gy = ((int)g2[-1] - (int)g0[-1]) + 2 * ((int)g2[0] - (int)g0[0]) + ((int)g2[1] - (int)g0[1]);
+            // g * (1/255) rounds to the same BF16 as g / 255 for every grey value g
+            const float c0 = (float)g1[0] * (float)(1.0 / 255.0);
+            const float c1 = sqrtf((float)(gx * gx + gy * gy)) / 1020.0f;
+            const float c2 = atan2f((float)gy, (float)gx) * inv_pi;
+            const float D = ds[r * kDW + x - 1];
+            float c3 = -4.0f;
+            if (D > 0.0f) c3 = (float)fmin(fmax(((double)D - fs[r]) / V.varpi, -4.0), 4.0);
+            pk.x = pack_bf16(c0, c1);
+            pk.y = pack_bf16(c2, c3);
+        }
+        *reinterpret_cast<uint2*>(feat + ((r + 1) * kXW + x) * 4) = pk;
+    }
+}
+
+// A disparity as the features see it: the value in pixels, or -1 where it is invalid.
+__device__ __forceinline__ float disp_value(const uint8_t* row, int u, int fmt) {
+    if (fmt == LD_DISP_U8) {
+        const int q = row[u];
+        return q != 0 ? (float)q : -1.0f;
+    } else if (fmt == LD_DISP_F32) {
+        const float x32 = reinterpret_cast<const float*>(row)[u];
+        return (isfinite(x32) && x32 > 0.0f) ? x32 : -1.0f;
+    }
+    const int q = reinterpret_cast<const uint16_t*>(row)[u];
+    return q != 0 ? (float)q * 0.0625f : -1.0f;                       // exact: q / 16
+}
+
+// Features of band rows top .. top+15, columns u0-3 .. u0+62 (x = 1 .. 66): I/255,
+// |grad|/1020, atan2(G_y, G_x)/pi, clamp((D - f(v)) / varpi, -4, 4) (-4 where D is invalid),
+// with the Sobel pair G_x = d/du, G_y = d/dv (weights 1, 2, 1, zero outside the frame).
+// The grey rows top-1 .. top+16 and the disparities are first staged in LDS (every load of
+// the workgroup in flight at once), then each pixel's features are formed from LDS.
 __device__ void build_features(const ldi_frame_view& V, int b, int top, int u0, const uint8_t* grey, int64_t gp,
                                const uint8_t* disp, int64_t dp, uint16_t* feat, unsigned char* stage) {
     const int W = V.W, H = V.H, t = threadIdx.x;
@@ -102,44 +159,55 @@ __device__ void build_features(const ldi_frame_view& V, int b, int top, int u0, 
     }
     for (int i = t; i < kBR * kDW; i += kT) {
         const int r = i / kDW, u = u0 - 3 + i % kDW;
-        float D = -1.0f;
-        if (u >= 0 && u < W) {
-            const uint8_t* row = db + (int64_t)(top + r) * dp;
-            if (V.fmt == LD_DISP_U8) {
-                const int q = row[u];
-                D = q != 0 ? (float)q : -1.0f;
-            } else if (V.fmt == LD_DISP_F32) {
-                const float x32 = reinterpret_cast<const float*>(row)[u];
-                D = (isfinite(x32) && x32 > 0.0f) ? x32 : -1.0f;
-            } else {
-                const int q = reinterpret_cast<const uint16_t*>(row)[u];
-                D = q != 0 ? (float)q * 0.0625f : -1.0f;                // exact: q / 16
-            }
-        }
-        ds[i] = D;
+        ds[i] = (u >= 0 && u < W) ? disp_value(db + (int64_t)(top + r) * dp, u, V.fmt) : -1.0f;
     }
     if (t < kBR) fs[t] = V.tab[(int64_t)b * 6 * H + top + t];
     __syncthreads();
-    const float inv_pi = (float)(1.0 / 3.14159265358979323846);
-    for (int i = t; i < kBR * 66; i += kT) {
-        const int r = i / 66, x = 1 + i % 66, u = u0 - 4 + x;
-        if (u < 0 || u >= W) continue;
-        const uint8_t* g0 = gs + r * kGW + x;          // row v-1, column u
-        const uint8_t* g1 = g0 + kGW;
-        const uint8_t* g2 = g1 + kGW;
-        const int gx = ((int)g0[1] - (int)g0[-1]) + 2 * ((int)g1[1] - (int)g1[-1]) + ((int)g2[1] - (int)g2[-1]);
-        const int gy = ((int)g2[-1] - (int)g0[-1]) + 2 * ((int)g2[0] - (int)g0[0]) + ((int)g2[1] - (int)g0[1]);
-        const float c0 = (float)g1[0] / 255.0f;
-        const float c1 = sqrtf((float)(gx * gx + gy * gy)) / 1020.0f;
-        const float c2 = atan2f((float)gy, (float)gx) * inv_pi;
-        const float D = ds[r * kDW + x - 1];
-        float c3 = -4.0f;
-        if (D > 0.0f) c3 = (float)fmin(fmax(((double)D - fs[r]) / V.varpi, -4.0), 4.0);
-        uint2 pk;
-        pk.x = bf16_bits(c0) | (bf16_bits(c1) << 16);
-        pk.y = bf16_bits(c2) | (bf16_bits(c3) << 16);
-        *reinterpret_cast<uint2*>(feat + ((r + 1) * kXW + x) * 4) = pk;
+    features_from_stage(V, u0, feat, stage);
+}
+
+// The raw inputs of one tile held in registers between units: thread t holds the staged
+// grey bytes t + 256k, the disparities t + 256k and (t < 16) f of band row t.
+constexpr int kRawG = (18 * kGW + kT - 1) / kT;
+constexpr int kRawD = (kBR * kDW + kT - 1) / kT;
+struct RawTile {
+    uint32_t g[kRawG];
+    float d[kRawD];
+    double f;
+};
+
+__device__ __forceinline__ void load_tile(const ldi_frame_view& V, int b, int top, int u0, const uint8_t* grey,
+                                          int64_t gp, const uint8_t* disp, int64_t dp, RawTile& R) {
+    const int W = V.W, H = V.H, t = threadIdx.x;
+    const uint8_t* gb = grey + (int64_t)b * H * gp;
+    const uint8_t* db = disp + (int64_t)b * H * dp;
+#pragma unroll
+    for (int k = 0; k < kRawG; ++k) {
+        const int i = t + k * kT;
+        const int r = i / kGW, u = u0 - 4 + i % kGW, v = top - 1 + r;
+        R.g[k] = (i < 18 * kGW && v >= 0 && v < H && u >= 0 && u < W) ? (uint32_t)gb[(int64_t)v * gp + u] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kRawD; ++k) {
+        const int i = t + k * kT;
+        const int r = i / kDW, u = u0 - 3 + i % kDW;
+        R.d[k] = (i < kBR * kDW && u >= 0 && u < W) ? disp_value(db + (int64_t)(top + r) * dp, u, V.fmt) : -1.0f;
+    }
+    R.f = t < kBR ? V.tab[(int64_t)b * 6 * H + top + t] : 0.0;
+}
+
+__device__ __forceinline__ void stage_tile(const RawTile& R, unsigned char* stage) {
+    const int t = threadIdx.x;
+    uint8_t* gs = stage;
+    float* ds = reinterpret_cast<float*>(stage + 18 * kGW);
+    double* fs = reinterpret_cast<double*>(ds + kBR * kDW);
+#pragma unroll
+    for (int k = 0; k < kRawG; ++k)
+        if (t + k * kT < 18 * kGW) gs[t + k * kT] = (uint8_t)R.g[k];
+#pragma unroll
+    for (int k = 0; k < kRawD; ++k)
+        if (t + k * kT < kBR * kDW) ds[t + k * kT] = R.d[k];
+    if (t < kBR) fs[t] = R.f;
 }
 
 __device__ __forceinline__ void zero_lds(uint4* p, int n16) {
@@ -190,10 +258,9 @@ __device__ void layer1(const uint16_t* feat, uint16_t* a1, const Net& N, int u0,
         const int u = u0 - 4 + x0 + n;
         const bool in = u >= 0 && u < W;
         uint2 o;
-        o.x = bf16_bits(in ? fmaxf(acc[0] + bias[0], 0.0f) : 0.0f) |
-              (bf16_bits(in ? fmaxf(acc[1] + bias[1], 0.0f) : 0.0f) << 16);
-        o.y = bf16_bits(in ? fmaxf(acc[2] + bias[2], 0.0f) : 0.0f) |
-              (bf16_bits(in ? fmaxf(acc[3] + bias[3], 0.0f) : 0.0f) << 16);
+        o.x = pack_bf16(fmaxf(acc[0] + bias[0], 0.0f), fmaxf(acc[1] + bias[1], 0.0f));
+        o.y = pack_bf16(fmaxf(acc[2] + bias[2], 0.0f), fmaxf(acc[3] + bias[3], 0.0f));
+        if (!in) o = make_uint2(0u, 0u);
         *reinterpret_cast<uint2*>(a1 + ((r + 1) * kXW + x0 + n) * 16 + 4 * g) = o;
     }
 }
@@ -239,11 +306,48 @@ __device__ __forceinline__ void store16(uint16_t* out, int xs, const f32x4 (&acc
         const int u = u0 - 4 + x0 + n;
         const bool in = u >= 0 && u < W;
         uint2 o;
-        o.x = bf16_bits(in ? fmaxf(acc[k][0] + bias[0], 0.0f) : 0.0f) |
-              (bf16_bits(in ? fmaxf(acc[k][1] + bias[1], 0.0f) : 0.0f) << 16);
-        o.y = bf16_bits(in ? fmaxf(acc[k][2] + bias[2], 0.0f) : 0.0f) |
-              (bf16_bits(in ? fmaxf(acc[k][3] + bias[3], 0.0f) : 0.0f) << 16);
+        o.x = pack_bf16(fmaxf(acc[k][0] + bias[0], 0.0f), fmaxf(acc[k][1] + bias[1], 0.0f));
+        o.y = pack_bf16(fmaxf(acc[k][2] + bias[2], 0.0f), fmaxf(acc[k][3] + bias[3], 0.0f));
+        if (!in) o = make_uint2(0u, 0u);
         *reinterpret_cast<uint2*>(out + ((r + 1) * kXW + x0 + n) * 16 + 4 * g) = o;
+    }
+}
+
+// 16-channel 3x3 convolution by a sweep over the input rows: wave w owns the 16 columns
+// x0 = xs + 16 w of all 16 output rows.  Input row ri is read as two operands,
+// P = [row ri, dx = -1 | row ri, dx = 0] and Q = [row ri, dx = +1 | row ri+1, dx = +1]; P feeds
+// output rows ri+1, ri, ri-1 (weights of dy = -1, 0, +1), Q feeds output row ri+1 (dy = -1, 0
+// of dx = +1) and output row ri-1 (dy = +1 of dx = +1, second half weighted zero).  Each output
+// row takes its nine taps once; rows 0 and 17 of `in` are zero.  A = 5 packed chunks
+// (P of dy = -1, 0, +1, then Q for row ri+1, Q for row ri-1).  acc[k] is LDS row k+1.
+__device__ __forceinline__ void conv_rows(const uint16_t* in, int xs, const uint4* A, f32x4 (&acc)[16]) {
+    const int lane = __lane_id(), wave = threadIdx.x / 64, n = lane & 15, g = lane >> 4;
+    uint4 Ac[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Ac[c] = A[c * 64 + lane];
+    const int x = xs + 16 * wave + n;
+    const uint16_t* pP = in + (x + (g < 2 ? -1 : 0)) * 16 + 8 * (g & 1);
+    const uint16_t* pQ = in + ((g < 2 ? 0 : kXW) + x + 1) * 16 + 8 * (g & 1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // operands of row ri+1 are read while row ri is multiplied; the scheduling barrier keeps
+    // the compiler from hoisting every row's reads (which would cost occupancy)
+    uint4 Qn = *reinterpret_cast<const uint4*>(pQ), Pn = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int ri = 0; ri <= 16; ++ri) {
+        const uint4 Q = Qn, P = Pn;
+        if (ri + 1 <= 16) {
+            Qn = *reinterpret_cast<const uint4*>(pQ + (ri + 1) * kXW * 16);
+            Pn = *reinterpret_cast<const uint4*>(pP + (ri + 1) * kXW * 16);
+        }
+        if (ri >= 1) {
+            if (ri + 1 <= 16) acc[ri] = mfma(Ac[0], P, acc[ri]);
+            acc[ri - 1] = mfma(Ac[1], P, acc[ri - 1]);
+            if (ri >= 2) acc[ri - 2] = mfma(Ac[2], P, acc[ri - 2]);
+        }
+        if (ri <= 15) acc[ri] = mfma(Ac[3], Q, acc[ri]);
+        if (ri >= 2) acc[ri - 2] = mfma(Ac[4], Q, acc[ri - 2]);
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -255,49 +359,86 @@ __device__ __forceinline__ int frame_band_top(const ldi_frame_view& V, int b, in
 
 // ------------------------------------------------------------------------------------------
 // Inference: decisions (z3 >= logit(theta)) into the frame's band buffer, optional P = sigmoid(z3).
-__global__ __launch_bounds__(kT) void k_cnn_fwd(ldi_frame_view V, Net N, int nb, float thr_logit,
+// A workgroup takes kFwdUnits consecutive units (column tile, band, frame), column tiles of one
+// band being consecutive units.  The raw inputs of the next unit are loaded into registers
+// while the current one is computed, and the feature buffer is cleared once (its rows 0 and
+// 17 are never written, every other cell read by layer 1 is written for each unit).
+constexpr int kFwdUnits = 4;
+
+__global__ __launch_bounds__(kT, 3) void k_cnn_fwd(ldi_frame_view V, Net N, int nb, float thr_logit,
                                                 const uint8_t* grey, int64_t gp, const uint8_t* disp, int64_t dp,
                                                 float* prob_out) {
     extern __shared__ uint4 smem4[];
     uint16_t* feat = reinterpret_cast<uint16_t*>(smem4);
     uint16_t* act = feat + kFeatElems;
-    const int ct = blockIdx.x, band = blockIdx.y, b = blockIdx.z, t = threadIdx.x;
-    if (V.nact != nullptr && b >= *V.nact) return;
-    const int W = V.W, u0 = ct * kCT;
-    const int top = frame_band_top(V, b, nb, band);
-    uint8_t* bits = V.lane_bits + ((int64_t)b * LDI_MAX_BANDS + band) * kBR * W;
-    float* prob = prob_out ? prob_out + ((int64_t)b * nb + band) * kBR * W : nullptr;
-    if (top < 0) {
-        for (int i = t; i < kBR * kCT; i += kT) {
-            const int r = i / kCT, u = u0 + i % kCT;
-            if (u < W) {
-                bits[r * W + u] = 0;
-                if (prob) prob[r * W + u] = 0.0f;
-            }
-        }
-        return;
+    unsigned char* stage = reinterpret_cast<unsigned char*>(act);    // the staged inputs live in act
+    const int t = threadIdx.x, W = V.W;
+    const int nct = (W + kCT - 1) / kCT;
+    const int nf = V.nact != nullptr ? min(*V.nact, V.active) : V.active;
+    const int total = nf * nb * nct;
+    const int first = blockIdx.x * kFwdUnits;
+    if (first >= total) return;
+    const int count = min(kFwdUnits, total - first);
+    __shared__ int tops[kFwdUnits];        // first band row of each unit, -1 without a band
+    if (t < count) {
+        const int q = (first + t) / nct;
+        tops[t] = frame_band_top(V, q / nb, nb, q % nb);
     }
     zero_lds(smem4, kFeatElems / 8);
-    build_features(V, b, top, u0, grey, gp, disp, dp, feat, reinterpret_cast<unsigned char*>(act));   // staged in act
     __syncthreads();
-    zero_act_border(act);
-    __syncthreads();
-    layer1(feat, act, N, u0, W);
-    __syncthreads();
-    f32x4 acc[16];
-    conv16(act, 3, N.wpk + 2 * 64, acc);
-    __syncthreads();                       // every tile has read a1: a2 replaces it in place
-    store16(act, 3, acc, N.master + kOffB2, u0, W);
-    __syncthreads();
-    conv16(act, 4, N.wpk + 7 * 64, acc);
+    RawTile R;
+    if (tops[0] >= 0) {
+        const int q = first / nct;
+        load_tile(V, q / nb, tops[0], (first % nct) * kCT, grey, gp, disp, dp, R);
+    }
     const int lane = __lane_id(), wave = t / 64, n = lane & 15;
-    if (lane < 16) {
-        const float b3 = N.master[kOffB3];
+#pragma unroll 1
+    for (int k = 0; k < count; ++k) {
+        const int unit = first + k, ct = unit % nct, q = unit / nct, band = q % nb, b = q / nb;
+        const int u0 = ct * kCT, top = tops[k];
+        uint8_t* bits = V.lane_bits + ((int64_t)b * LDI_MAX_BANDS + band) * kBR * W;
+        float* prob = prob_out ? prob_out + ((int64_t)b * nb + band) * kBR * W : nullptr;
+        if (top < 0) {
+            for (int i = t; i < kBR * kCT; i += kT) {
+                const int r = i / kCT, u = u0 + i % kCT;
+                if (u < W) {
+                    bits[r * W + u] = 0;
+                    if (prob) prob[r * W + u] = 0.0f;
+                }
+            }
+        } else {
+            __syncthreads();                   // the previous unit has finished reading act
+            stage_tile(R, stage);
+            __syncthreads();
+            features_from_stage(V, u0, feat, stage);
+        }
+        if (k + 1 < count) {                   // the next unit's inputs stay in flight below
+            const int un = unit + 1, qn = un / nct, tn = tops[k + 1];
+            if (tn >= 0) load_tile(V, qn / nb, tn, (un % nct) * kCT, grey, gp, disp, dp, R);
+        }
+        if (top < 0) continue;
+        __syncthreads();
+        zero_act_border(act);
+        __syncthreads();
+        layer1(feat, act, N, u0, W);
+        __syncthreads();
+        f32x4 acc[16];
+        conv_rows(act, 3, N.wpk + 18 * 64, acc);
+        __syncthreads();                       // every wave has read a1: a2 replaces it in place
+        store16(act, 3, acc, N.master + kOffB2, u0, W);
+        __syncthreads();
+        conv_rows(act, 4, N.wpk + 23 * 64, acc);
+        // layer 3 is packed into all 16 output rows of the tile, so every lane holds z of its
+        // pixel for every band row; lane group g writes rows g, g + 4, g + 8, g + 12
+        const int g = lane >> 4, col = 16 * wave + n, u = u0 + col;
+        if (col < kCT && u < W) {
+            const float b3 = N.master[kOffB3];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int tile = wave + 4 * k, r = tile >> 2, col = 16 * (tile & 3) + n, u = u0 + col;
-            if (col < kCT && u < W) {
-                const float z = acc[k][0] + b3;
+            for (int j = 0; j < 4; ++j) {
+                const float zr = g == 0 ? acc[4 * j][0] : g == 1 ? acc[4 * j + 1][0] : g == 2 ? acc[4 * j + 2][0]
+                                                                                             : acc[4 * j + 3][0];
+                const int r = 4 * j + g;
+                const float z = zr + b3;
                 bits[r * W + u] = z >= thr_logit ? 1 : 0;
                 if (prob) prob[r * W + u] = 1.0f / (1.0f + expf(-z));
             }
@@ -597,9 +738,18 @@ __global__ void k_cnn_pack(const float* w, uint4* wpk) {
         } else if (chunk == 12) {             // dL/da2: row = channel m, column = tap 8g + j
             const int tap = 8 * g + j;
             if (tap < 9) x = w[kOffW3 + tap * 16 + m];
-        } else {                              // dL/da1: row = input m, K = (tap 2c + g/2, output 8(g%2) + j)
+        } else if (chunk < 18) {              // dL/da1: row = input m, K = (tap 2c + g/2, output 8(g%2) + j)
             const int tap = 2 * (chunk - 13) + g / 2;
             if (tap < 9) x = w[kOffW2 + (tap * 16 + m) * 16 + 8 * (g & 1) + j];
+        } else {                              // row sweep, layer 2 (18 .. 22); layer 3 (23 .. 27) in all 16 rows
+            const int c = (chunk - 18) % 5, hi = g >= 2, in = 8 * (g & 1) + j;
+            int dy = 1, dx = 1;
+            bool zero = false;
+            if (c < 3) { dy = c - 1; dx = hi ? 0 : -1; }          // P of dy: dx = -1 | dx = 0
+            else if (c == 3) { dy = hi ? 0 : -1; }                 // Q for row ri+1: dy = -1 | dy = 0
+            else zero = hi;                                        // Q for row ri-1: dy = +1 | zero
+            const int tap = (dy + 1) * 3 + (dx + 1);
+            if (!zero) x = chunk < 23 ? w[kOffW2 + (tap * 16 + in) * 16 + m] : w[kOffW3 + tap * 16 + in];
         }
         h[j] = bf16_bits(x);
     }
@@ -704,8 +854,9 @@ ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, co
     const float thr_logit = (float)std::log(th / (1.0 - th));
     allow_lds(k_cnn_fwd, kFwdLds);
     Net N{n->wpk, n->master};
-    hipLaunchKernelGGL(k_cnn_fwd, dim3(col_tiles(V.W), nb, V.active), dim3(kT), kFwdLds, st, V, N, nb, thr_logit,
-                       grey, gp, static_cast<const uint8_t*>(disp), dp, prob_out);
+    const int64_t units = (int64_t)col_tiles(V.W) * nb * V.active;
+    hipLaunchKernelGGL(k_cnn_fwd, dim3((unsigned)((units + kFwdUnits - 1) / kFwdUnits)), dim3(kT), kFwdLds, st, V, N,
+                       nb, thr_logit, grey, gp, static_cast<const uint8_t*>(disp), dp, prob_out);
     s = hip_ok(hipGetLastError());
     if (s == LD_OK) s = ldi_frame_mark_bands(f, nb, st);
     n->last = st;
