@@ -1515,15 +1515,18 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 // Windowed V_px search: band accumulator and row DP on columns lo..hi only (transitions
 // leaving the window are not allowed), the same tie order as the full DP, backtrace, a check
 // that the path never reaches an inner edge of the window.  One wave per frame: lane l keeps
-// window columns 4l .. 4l+3 (E of the previous row and the column counts) in registers and
-// takes the neighbours' E from lanes l-2 .. l+2 by shuffles, so a row needs no barrier; the
-// band deltas of a row go through LDS atomics, from the road rows' vote columns staged in LDS
-// before the sweep; the backtrace (tau + 5, 4 bits per column,
+// window columns 4l .. 4l+3 (16 E of the previous row and the column counts) in registers and
+// takes the neighbours' values from lanes l-2 .. l+2 by DPP wave shifts, so a row needs no
+// barrier; the band deltas of a row go through LDS atomics, from the road rows' vote columns
+// staged in LDS before the sweep; the backtrace (the rank of tau, 4 bits per column,
 // 128 B per row) goes to the frame's backtrace buffer and is walked through LDS 32 rows at a
 // time.  Needs W >= 128 (the buffer holds W bytes per row); narrower frames use the full search.
 constexpr int kWalkChunk = 32;
 
 __device__ __forceinline__ int shfl_i(int x, int src) { return __shfl(x, src, kWave); }
+// x of lane l - 1 (kBig on lane 0) and of lane l + 1 (kBig on lane 63): DPP wave shifts by one
+__device__ __forceinline__ int lane_prev(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int lane_next(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x130, 0xF, 0xF, false); }
 
 __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
     extern __shared__ unsigned char smem[];
@@ -1615,15 +1618,20 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
         }
     };
     for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1);
-    int h[4], E[4];
+    // S = 16 E of the own columns (kBig outside the window).  A candidate from column c + tau
+    // costs S(c + tau) + slope |tau| - [tau < 0] with slope = 16 lambda + 2, i.e. 16 (E + lambda
+    // |tau|) plus the rank of tau in the tie order 0, -1, +1, -2, +2, ..., so one min picks the
+    // cost and the tie; offsets are taken relative to the lane's first column 4l.
+    int h[4], S[4];
     {
         const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
         h[0] = q.x; h[1] = q.y; h[2] = q.z; h[3] = q.w;
         *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) E[j] = 4 * l + j < win ? -h[j] : kBig;
-    const int tau_max = d.P.tau_x_max, lam = d.P.lambda_x;
+    for (int j = 0; j < 4; ++j) S[j] = 4 * l + j < win ? -16 * h[j] : kBig;
+    const int tau_max = d.P.tau_x_max, slope = 16 * d.P.lambda_x + 2;
+    const bool full5 = tau_max == 5;
     for (int v = v_max - 1; v >= v_h; --v) {
         if (v - chi >= v_h) apply(v - chi, 1);
         if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
@@ -1631,34 +1639,41 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
         const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
         *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
         h[0] += q.x; h[1] += q.y; h[2] += q.z; h[3] += q.w;
-        // E of columns 4l-8 .. 4l+11 of the previous row (kBig outside the window)
-        int nb[20];
+        // w[p] = S of column 4l - 5 + p of the previous row (p = 0 .. 13)
+        int w[14];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int a = shfl_i(E[j], l - 2), bb = shfl_i(E[j], l - 1), c = shfl_i(E[j], l + 1), e2 = shfl_i(E[j], l + 2);
-            nb[j] = l >= 2 ? a : kBig;
-            nb[4 + j] = l >= 1 ? bb : kBig;
-            nb[8 + j] = E[j];
-            nb[12 + j] = l + 1 < kWave ? c : kBig;
-            nb[16 + j] = l + 2 < kWave ? e2 : kBig;
+            w[1 + j] = lane_prev(S[j]);
+            w[5 + j] = S[j];
+            w[9 + j] = lane_next(S[j]);
+        }
+        w[0] = lane_prev(w[4]);
+        w[13] = lane_next(w[9]);
+        int TL[14], TR[14];
+#pragma unroll
+        for (int p = 0; p < 14; ++p) {
+            const int off = slope * (p - 5);
+            TL[p] = w[p] - off;
+            TR[p] = w[p] + off;
         }
         uint32_t bits = 0;
-        int En[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int best = nb[8 + j], bt = 0;
+            int lm, rm;
+            if (full5) {
+                lm = min(min(min(TL[j], TL[j + 1]), min(TL[j + 2], TL[j + 3])), TL[j + 4]);
+                rm = min(min(min(TR[j + 6], TR[j + 7]), min(TR[j + 8], TR[j + 9])), TR[j + 10]);
+            } else {
+                lm = kBig; rm = kBig;
 #pragma unroll
-            for (int a = 1; a <= 5; ++a) {
-                if (a > tau_max) break;
-                const int left = nb[8 + j - a] + lam * a, right = nb[8 + j + a] + lam * a;
-                if (left < best) { best = left; bt = -a; }
-                if (right < best) { best = right; bt = a; }
+                for (int a = 1; a <= 5; ++a)
+                    if (a <= tau_max) { lm = min(lm, TL[j + 5 - a]); rm = min(rm, TR[j + 5 + a]); }
             }
-            En[j] = 4 * l + j < win ? -h[j] + best : kBig;
-            bits |= (uint32_t)(bt + 5) << (4 * j);
+            const int cc = slope * j;
+            const int key = min(w[5 + j], min(lm + (cc - 1), rm - cc));
+            S[j] = 4 * l + j < win ? (key & ~15) - 16 * h[j] : kBig;
+            bits |= (uint32_t)(key & 15) << (4 * j);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) E[j] = En[j];
         back[(int64_t)(v - v_h) * kWave + l] = (uint16_t)bits;
     }
     // start column: argmin over the window of E at v_h, ties to the smaller column
@@ -1666,7 +1681,7 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
     int bc = 0x7fffffff;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (4 * l + j < win && (int64_t)E[j] < bv) { bv = E[j]; bc = 4 * l + j; }
+        if (4 * l + j < win && (int64_t)(S[j] >> 4) < bv) { bv = S[j] >> 4; bc = 4 * l + j; }
     wave_argmin_i64(bv, bc);
     __threadfence_block();   // the backtrace stores are complete before the wave reads them back
     int c = bc, touch = 0;
@@ -1678,7 +1693,7 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
             for (int v = v0; v <= last; ++v) {
                 if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
                 path[v] = lo + c;
-                if (v < v_max) c += (int)((stage[(v - v0) * kWave + (c >> 2)] >> (4 * (c & 3))) & 15u) - 5;
+                if (v < v_max) c += rank_to_tau((int)((stage[(v - v0) * kWave + (c >> 2)] >> (4 * (c & 3))) & 15u));
             }
             path[H] = touch;
         }
