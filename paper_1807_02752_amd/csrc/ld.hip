@@ -1632,9 +1632,51 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
     for (int j = 0; j < 4; ++j) S[j] = 4 * l + j < win ? -16 * h[j] : kBig;
     const int tau_max = d.P.tau_x_max, slope = 16 * d.P.lambda_x + 2;
     const bool full5 = tau_max == 5;
+    // With the vote columns staged, the band changes of row v (votes of row v - chi entering,
+    // of row v + chi + 1 leaving) are read ahead: the list heads (count, offset) two rows
+    // ahead and the first 64 window offsets of each list one row ahead, so a row waits for
+    // one LDS round trip (its deltas) before the DP.
+    int nA2 = 0, oA2 = 0, nR2 = 0, oR2 = 0;        // list heads of row v - 1
+    int nA1 = 0, oA1 = 0, nR1 = 0, oR1 = 0;        // list heads of row v
+    int kA = -1, kR = -1;                          // own entries of row v's lists (-1: none)
+    auto heads = [&](int r, int& nA, int& oA, int& nR, int& oR) {
+        const int ra = r - chi, rr = r + chi + 1;
+        nA = (r >= v_h && ra >= v_h) ? cntL[max(ra, 0)] : 0;
+        oA = roff[max(ra - v_h, 0)];
+        nR = (r >= v_h && rr <= v_max) ? cntL[min(rr, v_max)] : 0;
+        oR = roff[min(max(rr - v_h, 0), R)];
+    };
+    auto own_key = [&](int n, int o) -> int {
+        if (l >= n) return -1;
+        const int c = wb[o + l];
+        return c != 255 ? c : -1;
+    };
+    if (staged) {
+        heads(v_max - 1, nA1, oA1, nR1, oR1);
+        heads(v_max - 2, nA2, oA2, nR2, oR2);
+        kA = own_key(nA1, oA1);
+        kR = own_key(nR1, oR1);
+    }
     for (int v = v_max - 1; v >= v_h; --v) {
-        if (v - chi >= v_h) apply(v - chi, 1);
-        if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
+        if (staged) {
+            if (kA >= 0) atomicAdd(&dlt[kA], 1);
+            if (kR >= 0) atomicAdd(&dlt[kR], -1);
+            for (int i = l + kWave; i < nA1; i += kWave) {
+                const int c = wb[oA1 + i];
+                if (c != 255) atomicAdd(&dlt[c], 1);
+            }
+            for (int i = l + kWave; i < nR1; i += kWave) {
+                const int c = wb[oR1 + i];
+                if (c != 255) atomicAdd(&dlt[c], -1);
+            }
+            kA = own_key(nA2, oA2);                 // row v - 1
+            kR = own_key(nR2, oR2);
+            nA1 = nA2; oA1 = oA2; nR1 = nR2; oR1 = oR2;
+            heads(v - 2, nA2, oA2, nR2, oR2);
+        } else {
+            if (v - chi >= v_h) apply(v - chi, 1);
+            if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
+        }
         // the wave's LDS operations complete in order: the deltas are final here
         const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
         *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
