@@ -42,6 +42,7 @@ struct FrameInfo {
 
 constexpr int kMaxRounds = 64;
 constexpr int kBig = 0x3FFFFFFF;
+constexpr int kMaxLds = 160 * 1024;   // LDS bytes a workgroup may hold on gfx950
 
 // Device view of a frame object: sizes, parameters and the scratch carried between steps.
 struct Dev {
@@ -1528,10 +1529,13 @@ __device__ __forceinline__ int shfl_i(int x, int src) { return __shfl(x, src, kW
 __device__ __forceinline__ int lane_prev(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x138, 0xF, 0xF, false); }
 __device__ __forceinline__ int lane_next(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x130, 0xF, 0xF, false); }
 
-__global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
-    extern __shared__ unsigned char smem[];
-    const int b = blockIdx.x, l = lane_id();
-    if (frame_masked(d, b)) return;
+__global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wave_bytes, int nframes) {
+    extern __shared__ unsigned char smem_all[];
+    // blockDim.x / 64 frames per workgroup, one per wave with its own LDS slice: the waves of
+    // a workgroup go to different SIMDs, so a batch of four frames per CU runs one wave per SIMD
+    const int b = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave, l = lane_id();
+    if (b >= nframes || frame_masked(d, b)) return;
+    unsigned char* smem = smem_all + (size_t)(threadIdx.x / kWave) * wave_bytes;
     int32_t* pr = d.prune + (int64_t)b * kPruneWords;
     if (pr[1] & kFbPlainVpx) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
@@ -1543,8 +1547,8 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
     int* cntL = dlt + 256;                                    // H
     int* path = cntL + H;                                     // H + 1 (the last: touch flag)
     int* roff = path + H + 1;                                 // R + 1 <= H + 1
-    uint16_t* stage = reinterpret_cast<uint16_t*>(roff + H + 1);          // kWalkChunk x 64
-    uint8_t* wb = reinterpret_cast<uint8_t*>(stage + kWave * kWalkChunk);  // stage_cap bytes
+    uint8_t* wb = reinterpret_cast<uint8_t*>(roff + H + 1);               // stage_cap bytes
+    uint16_t* stage = reinterpret_cast<uint16_t*>(wb);                    // kWalkChunk x 64, after the sweep
     uint16_t* back = reinterpret_cast<uint16_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 2;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
     for (int v = l; v < H; v += kWave) cntL[v] = d.rowcnt[(int64_t)b * H + v];
@@ -1587,10 +1591,21 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
                 nv += (c2[k][0] >= 0 ? 1 : 0) + (c2[k][1] >= 0 ? 1 : 0);
                 if (l < n) wb[o + l] = woff(c2[k][0]);
                 if (l + kWave < n) wb[o + l + kWave] = woff(c2[k][1]);
-                for (int i = l + 2 * kWave; i < n; i += kWave) {
-                    const int c = fe[(int64_t)v * d.W + i].bin;
-                    nv += c >= 0 ? 1 : 0;
-                    wb[o + i] = woff(c);
+                for (int i0 = l + 2 * kWave; i0 < n; i0 += 8 * kWave) {   // long rows: 8 loads in flight
+                    int cc[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int i = i0 + j * kWave;
+                        cc[j] = i < n ? fe[(int64_t)v * d.W + i].bin : -1;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int i = i0 + j * kWave;
+                        if (i < n) {
+                            nv += cc[j] >= 0 ? 1 : 0;
+                            wb[o + i] = woff(cc[j]);
+                        }
+                    }
                 }
             }
         }
@@ -1661,13 +1676,20 @@ __global__ __launch_bounds__(64) void k_vpx_window(Dev d, int stage_cap) {
         if (staged) {
             if (kA >= 0) atomicAdd(&dlt[kA], 1);
             if (kR >= 0) atomicAdd(&dlt[kR], -1);
-            for (int i = l + kWave; i < nA1; i += kWave) {
-                const int c = wb[oA1 + i];
-                if (c != 255) atomicAdd(&dlt[c], 1);
-            }
-            for (int i = l + kWave; i < nR1; i += kWave) {
-                const int c = wb[oR1 + i];
-                if (c != 255) atomicAdd(&dlt[c], -1);
+            // long lists: four offsets read before their atomics
+            for (int i0 = l + kWave; i0 < max(nA1, nR1); i0 += 2 * kWave) {
+                int ca[2], cr[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int i = i0 + j * kWave;
+                    ca[j] = i < nA1 ? wb[oA1 + i] : 255;
+                    cr[j] = i < nR1 ? wb[oR1 + i] : 255;
+                }
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (ca[j] != 255) atomicAdd(&dlt[ca[j]], 1);
+                    if (cr[j] != 255) atomicAdd(&dlt[cr[j]], -1);
+                }
             }
             kA = own_key(nA2, oA2);                 // row v - 1
             kR = own_key(nR2, oR2);
@@ -2322,10 +2344,13 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     }
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
-        const int cap = std::min(32768, std::max(4096, 16 * d.W));   // staged road edges (bytes)
-        const size_t lw = sizeof(int) * (256 + 3 * (size_t)d.H + 2) + sizeof(uint16_t) * kWave * kWalkChunk + cap;
-        allow_lds(k_vpx_window, lw);
-        hipLaunchKernelGGL(k_vpx_window, dim3(f->active), dim3(kWave), lw, st, d, cap);
+        const int cap = std::min(16384, std::max(4096, 16 * d.W));   // staged road edges (bytes)
+        const size_t lw = sizeof(int) * (256 + 3 * (size_t)d.H + 2) + cap;
+        const int wave_bytes = (int)((lw + 15) / 16 * 16);
+        const int fpw = std::max(1, std::min(4, kMaxLds / wave_bytes));   // frames per workgroup
+        allow_lds(k_vpx_window, (size_t)fpw * wave_bytes);
+        hipLaunchKernelGGL(k_vpx_window, dim3((f->active + fpw - 1) / fpw), dim3(kWave * fpw), (size_t)fpw * wave_bytes,
+                           st, d, cap, wave_bytes, f->active);
         s = launch_ok();
     }
     Dev full = d;                       // frames sent back to the full V_px search
