@@ -192,6 +192,9 @@ const char* ld_status_string(ld_status s);
  *                      its inlier count, points in the round), beta then gamma
  *   LD_STATE_LANE_BITS uint8[4 * 16 * width]: network decisions of the last
  *                      ld_cnn_forward / ld_detect_pruned, band k at k * 16 * width
+ *                      (ld_detect_pruned without the candidate mask, dilate < 0, evaluates
+ *                      only the 60-column tiles whose band rows hold a voting road edge,
+ *                      the only pixels it reads; the other tiles hold 0)
  *   LD_STATE_PRUNE     int32[16] of the last ld_detect_pruned: bands, fallback bits (1 plain
  *                      V_px search, 2 plain energies, 4 no seed, 8 window edge touched),
  *                      seed column c_s (-1 none), window lo, hi, pooled marking votes,
@@ -299,7 +302,8 @@ ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t g
                             float* loss_out, float* grad_out, void* hip_stream);
 
 /* The whole path with the network narrowing the search, for the active frames of f:
- *  1. ld_vdisp, the network's band decisions, edges and votes as in ld_detect;
+ *  1. ld_vdisp, edges and votes as in ld_detect, the network's band decisions (with
+ *     dilate < 0 only on the 60-column tiles of a band that hold a voting road edge);
  *  2. seed: the votes of marking edges in the bands, histogrammed per band; the pooled
  *     histogram's argmax c_s (ties to the smaller column) centres the window
  *     [c_s - delta_x, c_s + delta_x] of V_px columns; with seed_ransac, RANSAC hypothesis 0

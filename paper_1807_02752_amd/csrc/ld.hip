@@ -2329,11 +2329,13 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
     f->stage = s == LD_OK ? 1 : 0;
     f->bands = 0;
+    // the edges first: without the candidate mask the network decisions are read only at voting
+    // road edges of the band rows, so the network skips the column tiles that hold none
+    if (s == LD_OK) s = run_edges(f, grey, grey_pitch, disp, disp_pitch, st);
     if (s == LD_OK) {
         ProfScope ps(f, 6, st);
-        s = ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, nullptr, st);
+        s = ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, nullptr, c->dilate < 0 ? 1 : 0, st);
     }
-    if (s == LD_OK) s = run_edges(f, grey, grey_pitch, disp, disp_pitch, st);
     if (s == LD_OK) {
         ProfScope ps(f, 7, st);
         const size_t ls = sizeof(int) * 2 * (size_t)d.W2;
@@ -2472,6 +2474,8 @@ ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v) {
     v->info = reinterpret_cast<const int32_t*>(d.info);
     v->lane_bits = d.lbits;
     v->nact = d.nact;
+    v->edges = d.edges;
+    v->rowcnt = d.rowcnt;
     return LD_OK;
 }
 

@@ -362,12 +362,15 @@ __device__ __forceinline__ int frame_band_top(const ldi_frame_view& V, int b, in
 // A workgroup takes kFwdUnits consecutive units (column tile, band, frame), column tiles of one
 // band being consecutive units.  The raw inputs of the next unit are loaded into registers
 // while the current one is computed, and the feature buffer is cleared once (its rows 0 and
-// 17 are never written, every other cell read by layer 1 is written for each unit).
+// 17 are never written, every other cell read by layer 1 is written for each unit).  With
+// `sparse`, a unit is evaluated only when a voting road edge (vote column >= 0) lies on its
+// band rows and output columns; the others get zero decisions and load nothing.
 constexpr int kFwdUnits = 4;
+static_assert(kT / 64 == kFwdUnits, "wave w checks unit w");
 
 __global__ __launch_bounds__(kT, 3) void k_cnn_fwd(ldi_frame_view V, Net N, int nb, float thr_logit,
                                                 const uint8_t* grey, int64_t gp, const uint8_t* disp, int64_t dp,
-                                                float* prob_out) {
+                                                float* prob_out, int sparse) {
     extern __shared__ uint4 smem4[];
     uint16_t* feat = reinterpret_cast<uint16_t*>(smem4);
     uint16_t* act = feat + kFeatElems;
@@ -380,14 +383,41 @@ __global__ __launch_bounds__(kT, 3) void k_cnn_fwd(ldi_frame_view V, Net N, int 
     if (first >= total) return;
     const int count = min(kFwdUnits, total - first);
     __shared__ int tops[kFwdUnits];        // first band row of each unit, -1 without a band
+    __shared__ int need[kFwdUnits];        // the unit is evaluated
     if (t < count) {
         const int q = (first + t) / nct;
         tops[t] = frame_band_top(V, q / nb, nb, q % nb);
     }
     zero_lds(smem4, kFeatElems / 8);
     __syncthreads();
+    {   // sparse: wave w looks for a voting road edge on the band rows and columns of unit w
+        const int w = t / 64, l = t % 64;
+        bool any = !sparse;
+        if (sparse && w < count && tops[w] >= 0) {
+            const int unit = first + w, u0 = (unit % nct) * kCT;
+            const int64_t row0 = (int64_t)((unit / nct) / nb) * V.H + tops[w];
+            int cnt[kBR];
+            ld_edge e[kBR];
+#pragma unroll
+            for (int r = 0; r < kBR; ++r) {
+                cnt[r] = V.rowcnt[row0 + r];
+                e[r] = V.edges[(row0 + r) * W + min(l, W - 1)];
+            }
+#pragma unroll
+            for (int r = 0; r < kBR; ++r)
+                any = any || (l < cnt[r] && e[r].bin >= 0 && e[r].u >= u0 && e[r].u < u0 + kCT);
+            for (int r = 0; r < kBR; ++r)
+                for (int i = l + 64; i < cnt[r]; i += 64) {
+                    const ld_edge x = V.edges[(row0 + r) * W + i];
+                    any = any || (x.bin >= 0 && x.u >= u0 && x.u < u0 + kCT);
+                }
+        }
+        any = __any(any ? 1 : 0) != 0;
+        if (l == 0 && w < kFwdUnits) need[w] = any ? 1 : 0;
+    }
+    __syncthreads();
     RawTile R;
-    if (tops[0] >= 0) {
+    if (tops[0] >= 0 && need[0]) {
         const int q = first / nct;
         load_tile(V, q / nb, tops[0], (first % nct) * kCT, grey, gp, disp, dp, R);
     }
@@ -395,7 +425,7 @@ __global__ __launch_bounds__(kT, 3) void k_cnn_fwd(ldi_frame_view V, Net N, int 
 #pragma unroll 1
     for (int k = 0; k < count; ++k) {
         const int unit = first + k, ct = unit % nct, q = unit / nct, band = q % nb, b = q / nb;
-        const int u0 = ct * kCT, top = tops[k];
+        const int u0 = ct * kCT, top = need[k] ? tops[k] : -1;
         uint8_t* bits = V.lane_bits + ((int64_t)b * LDI_MAX_BANDS + band) * kBR * W;
         float* prob = prob_out ? prob_out + ((int64_t)b * nb + band) * kBR * W : nullptr;
         if (top < 0) {
@@ -413,7 +443,7 @@ __global__ __launch_bounds__(kT, 3) void k_cnn_fwd(ldi_frame_view V, Net N, int 
             features_from_stage(V, u0, feat, stage);
         }
         if (k + 1 < count) {                   // the next unit's inputs stay in flight below
-            const int un = unit + 1, qn = un / nct, tn = tops[k + 1];
+            const int un = unit + 1, qn = un / nct, tn = need[k + 1] ? tops[k + 1] : -1;
             if (tn >= 0) load_tile(V, qn / nb, tn, (un % nct) * kCT, grey, gp, disp, dp, R);
         }
         if (top < 0) continue;
@@ -845,7 +875,7 @@ ld_status check_frame(ld_cnn n, ld_frame f, ldi_frame_view& V, const uint8_t* gr
 
 // Internal: decisions of the network into the frame's band buffer (used by ld_detect_pruned).
 ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dp,
-                       float* prob_out, hipStream_t st) {
+                       float* prob_out, int sparse, hipStream_t st) {
     ldi_frame_view V;
     ld_status s = check_frame(n, f, V, grey, gp, disp, dp);
     if (s != LD_OK) return s;
@@ -856,7 +886,7 @@ ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, co
     Net N{n->wpk, n->master};
     const int64_t units = (int64_t)col_tiles(V.W) * nb * V.active;
     hipLaunchKernelGGL(k_cnn_fwd, dim3((unsigned)((units + kFwdUnits - 1) / kFwdUnits)), dim3(kT), kFwdLds, st, V, N,
-                       nb, thr_logit, grey, gp, static_cast<const uint8_t*>(disp), dp, prob_out);
+                       nb, thr_logit, grey, gp, static_cast<const uint8_t*>(disp), dp, prob_out, sparse);
     s = hip_ok(hipGetLastError());
     if (s == LD_OK) s = ldi_frame_mark_bands(f, nb, st);
     n->last = st;
@@ -948,7 +978,7 @@ ld_status ld_cnn_get_params(ld_cnn n, float* params) {
 ld_status ld_cnn_forward(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                          int64_t disp_pitch, float* prob_out, void* hip_stream) {
     if (prob_out && ((uintptr_t)prob_out % 4) != 0) return LD_E_INVAL;
-    return ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, prob_out, static_cast<hipStream_t>(hip_stream));
+    return ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, prob_out, 0, static_cast<hipStream_t>(hip_stream));
 }
 
 ld_status ld_cnn_labels(ld_cnn n, ld_frame f, const ld_lanes* lanes, const float* curves, float radius,

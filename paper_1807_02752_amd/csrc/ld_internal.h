@@ -29,6 +29,8 @@ typedef struct {
     const int32_t* info;      /* batch x 8: flags, v_h, ... */
     uint8_t* lane_bits;       /* batch x LDI_MAX_BANDS x LDI_BAND_ROWS x W: network decisions */
     const int32_t* nact;      /* nullable active-frame count on the device */
+    const ld_edge* edges;     /* batch x H x W: road edges of each row (after the edge kernel) */
+    const int32_t* rowcnt;    /* batch x H: road edges per row */
 } ldi_frame_view;
 
 ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v);
@@ -44,6 +46,8 @@ __host__ __device__ inline int ldi_band_top(int v_h, int H, int n_bands, int k) 
 }
 
 // Network decisions for the active frames of f into its band buffer (ld_cnn.hip).
+// With sparse set (the edge kernel has run), only the column tiles whose band rows hold a
+// voting road edge are evaluated; the others get zero decisions.
 ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dp,
-                       float* prob_out, hipStream_t st);
+                       float* prob_out, int sparse, hipStream_t st);
 const ld_cnn_config* ldi_cnn_config(ld_cnn n);
