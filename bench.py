@@ -90,15 +90,16 @@ def make_serving_pool(procs: int):
     return classes, frames
 
 
-def serving_leg(args, pool):
+def serving_leg(args, pool, net=None):
     """Continuous batching: every stream submits frames as Poisson arrivals at 30 fps for
     serve_seconds of wall time while the host polls; latency is arrival to host-visible
-    result."""
+    result.  With `net` the engines run the pruned path (plain fallback per frame)."""
     import torch
     from paper_1807_02752_amd import ld
     classes, frames = pool
     dev = [[(torch.from_numpy(gr).cuda(), torch.from_numpy(dp).cuda()) for gr, dp in fr] for fr in frames]
-    cfg = ld.server_config(SERVE_CLASSES, n_streams=SERVE_STREAMS, inflight=2, max_queue=1024, use_graphs=True)
+    cfg = ld.server_config(SERVE_CLASSES, n_streams=SERVE_STREAMS, inflight=2, max_queue=1024, use_graphs=True,
+                           cnn=net)
     srv = ld.Server(cfg)
     rng = np.random.default_rng(11)
     T = args.serve_seconds
@@ -138,7 +139,7 @@ def serving_leg(args, pool):
     return {"streams": SERVE_STREAMS, "offered_fps": len(arrivals) / T, "achieved_fps": done / wall,
             "requests": done, "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
             "classes": [f"{w}x{h}" for w, h, *_ in SERVE_CLASSES], "streams_per_class": [classes.count(c) for c in range(3)],
-            "engines_per_class": pc[:3], "engine_bytes": mem, "graphs": True, "pruning": False}
+            "engines_per_class": pc[:3], "engine_bytes": mem, "graphs": True, "pruning": net is not None}
 
 
 def learned_leg(args, det, g, d, lanes, plain_lanes, tgreys, tdisps, plain_ms):
@@ -186,10 +187,9 @@ def learned_leg(args, det, g, d, lanes, plain_lanes, tgreys, tdisps, plain_ms):
                        "dilate": cfg.dilate, "seed_ransac": cfg.seed_ransac, "params": ld.LD_CNN_PARAMS},
            "train": {"steps": args.train_steps, "batch": 16, "frames": int(tgreys.shape[0]), "seconds": round(train_s, 2),
                      "loss_first10": float(losses[:10].mean()), "loss_last10": float(losses[-10:].mean())}}
-    net.close()
     log(f"pruned: {ms:.3f} ms/step ({plain_ms / ms:.2f}x plain), disagreement {res['lane_disagreement']:.4f}, "
         f"fallback {res['fallback_frac']:.3f}")
-    return res
+    return res, net
 
 
 def cpu_baseline(greys, disps, seconds: float, threads: int):
@@ -350,10 +350,13 @@ def main():
         "lanes_per_frame": float(lanes_np["n"].mean()),
         "learned_pruned": None,
     }
+    net = None
     if args.train_steps > 0:
-        out["learned_pruned"] = learned_leg(args, det, g, d, lanes, lanes_np, tgreys, tdisps, ms_per_step)
+        out["learned_pruned"], net = learned_leg(args, det, g, d, lanes, lanes_np, tgreys, tdisps, ms_per_step)
     if serve_pool is not None:
-        out["serving"] = serving_leg(args, serve_pool)
+        out["serving"] = serving_leg(args, serve_pool, net)
+    if net is not None:
+        net.close()
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(greys, disps, args.cpu_seconds, threads)

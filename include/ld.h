@@ -359,6 +359,9 @@ typedef struct ld_server_config {
     int32_t use_graphs;                     /* 1: replay a captured graph per engine */
     int32_t seed_from_state;                /* 1: seed V_px RANSAC with the stream's last fit */
     int64_t hbm_budget;                     /* bytes of device memory the engines may use */
+    ld_cnn cnn;                             /* nullable: run ld_detect_pruned with this network
+                                               (plain fallback per frame, seed_from_state not
+                                               used); read only, must outlive the server */
 } ld_server_config;
 
 /* One finished request.  Times are host seconds (steady clock) at submit and at the poll

@@ -135,17 +135,27 @@ void free_engine(Engine* e) {
 }
 
 // The device part of one batch, enqueued on the engine's stream: seeds from the stream
-// table, the four steps, the state update and the copy of the lanes to pinned memory.
+// table, the four steps (or the pruned path with the server's network), the state update and
+// the copy of the lanes to pinned memory.
 ld_status enqueue_batch_body(ld_server s, Engine* e) {
     const int B = e->B;
     const int64_t gp = e->W, dpt = (int64_t)e->W * e->es;
-    const bool seed = s->cfg.seed_from_state != 0;
-    if (seed) hipLaunchKernelGGL(k_gather_seeds, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact, e->d_seed);
-    ld_status r = ld_vdisp(e->f, e->d_disp, dpt, e->d_sid, e->d_fidx, nullptr, nullptr, e->st);
-    if (r == LD_OK)
-        r = ld_vp_ransac(e->f, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx, seed ? e->d_seed : nullptr, nullptr, e->st);
-    if (r == LD_OK) r = ld_lane_energy(e->f, nullptr, nullptr, e->st);
-    if (r == LD_OK) r = ld_peaks(e->f, e->d_lanes, nullptr, e->st);
+    ld_status r = LD_OK;
+    if (s->cfg.cnn) {
+        r = ld_detect_pruned(e->f, s->cfg.cnn, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx, e->d_lanes, nullptr,
+                             e->st);
+    } else {
+        const bool seed = s->cfg.seed_from_state != 0;
+        if (seed)
+            hipLaunchKernelGGL(k_gather_seeds, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact,
+                               e->d_seed);
+        r = ld_vdisp(e->f, e->d_disp, dpt, e->d_sid, e->d_fidx, nullptr, nullptr, e->st);
+        if (r == LD_OK)
+            r = ld_vp_ransac(e->f, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx, seed ? e->d_seed : nullptr, nullptr,
+                             e->st);
+        if (r == LD_OK) r = ld_lane_energy(e->f, nullptr, nullptr, e->st);
+        if (r == LD_OK) r = ld_peaks(e->f, e->d_lanes, nullptr, e->st);
+    }
     if (r != LD_OK) return r;
     hipLaunchKernelGGL(k_store_state, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact, ldi_frame_fits(e->f));
     return hipGetLastError() == hipSuccess ? LD_OK : LD_E_HIP;

@@ -63,7 +63,7 @@ class ld_server_config(C.Structure):
                 ("fmt", C.c_int32 * LD_MAX_CLASSES), ("d_max", C.c_int32 * LD_MAX_CLASSES),
                 ("max_batch", C.c_int32 * LD_MAX_CLASSES), ("n_streams", C.c_int32), ("inflight", C.c_int32),
                 ("max_queue", C.c_int32), ("use_graphs", C.c_int32), ("seed_from_state", C.c_int32),
-                ("hbm_budget", C.c_int64)]
+                ("hbm_budget", C.c_int64), ("cnn", C.c_void_p)]
 
 
 class ld_server_result(C.Structure):
@@ -309,9 +309,11 @@ def cnn_config(**overrides) -> ld_cnn_config:
 
 
 def server_config(classes, *, n_streams=32, inflight=2, max_queue=256, use_graphs=True, seed_from_state=True,
-                  hbm_budget=64 << 30):
-    """classes: list of (width, height, fmt, d_max, max_batch)."""
+                  hbm_budget=64 << 30, cnn=None):
+    """classes: list of (width, height, fmt, d_max, max_batch).  cnn: a Cnn whose network runs
+    the pruned path (it must stay open while the server lives)."""
     cfg = ld_server_config()
+    cfg.cnn = cnn.handle if cnn is not None else None
     cfg.n_classes = len(classes)
     for k, (w, h, f, dm, mb) in enumerate(classes):
         cfg.width[k], cfg.height[k], cfg.fmt[k], cfg.d_max[k], cfg.max_batch[k] = w, h, f, dm, mb

@@ -60,9 +60,41 @@ def _sequential(frames, s):
     return res
 
 
-def _serve(frames, use_graphs, order):
+def _bright_net():
+    """A hand-set network that marks bright pixels (z = 20 ReLU(I/255 - 0.6) - 1 at the centre taps)."""
+    from oracle import cnn
+    p = {k: np.zeros(s) for k, s in cnn.ORDER}
+    p["w1"][1, 1, 0, 0] = 1.0
+    p["b1"][0] = -0.6
+    p["w2"][1, 1, 0, 0] = 1.0
+    p["w3"][1, 1, 0, 0] = 20.0
+    p["b3"][0] = -1.0
+    return _ld().Cnn(cnn.flat(p).astype(np.float32))
+
+
+def _pruned_alone(frames, s, net):
+    """One stream alone, frame by frame, through ld_detect_pruned with the stream's ids."""
     ld = _ld()
-    cfg = ld.server_config(CLASSES, n_streams=len(frames), inflight=2, max_queue=64, use_graphs=use_graphs)
+    res = []
+    for k, (g, d, cls) in enumerate(frames):
+        W, H, fmt, dm, _ = CLASSES[cls]
+        det = ld.Detector(W, H, 1, fmt, dm)
+        gt = torch.from_numpy(g[None]).cuda()
+        dt = torch.from_numpy(d[None]).cuda()
+        sid = torch.tensor([s], dtype=torch.int64).cuda()
+        fid = torch.tensor([k], dtype=torch.int64).cuda()
+        lanes = det.lanes_buffer()
+        det.detect_pruned(net, gt, dt, lanes, stream_ids=sid, frame_idx=fid)
+        det.sync()
+        L = ld.Detector.parse_lanes(lanes)[0]
+        res.append((int(L["n"]), int(L["flags"]), list(L["u_start"][: L["n"]]), list(L["energy"][: L["n"]])))
+        det.close()
+    return res
+
+
+def _serve(frames, use_graphs, order, net=None):
+    ld = _ld()
+    cfg = ld.server_config(CLASSES, n_streams=len(frames), inflight=2, max_queue=64, use_graphs=use_graphs, cnn=net)
     srv = ld.Server(cfg)
     keep = []
     got = {s: {} for s in frames}
@@ -101,6 +133,26 @@ def test_server_equals_each_frame_alone(use_graphs):
             assert (r["n"], r["flags"], r["u_start"]) == (n, flags, us), (s, k)
             assert r["energy"] == es
             assert r["t_done"] >= r["t_submit"]
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_pruned_equals_each_frame_alone(use_graphs):
+    """With a network the server runs the pruned path; each frame's lanes (and fallback flags)
+    equal those of the frame run alone through ld_detect_pruned."""
+    frames = _frames(5, 4)
+    rng = np.random.default_rng(2)
+    order = [s for s in frames for _ in range(len(frames[s]))]
+    rng.shuffle(order)
+    net = _bright_net()
+    got = _serve(frames, use_graphs, order, net)
+    for s in frames:
+        want = _pruned_alone(frames[s], s, net)
+        assert sorted(got[s]) == list(range(len(frames[s])))
+        for k, (n, flags, us, es) in enumerate(want):
+            r = got[s][k]
+            assert (r["n"], r["flags"], r["u_start"]) == (n, flags, us), (s, k)
+            assert r["energy"] == es
+    net.close()
 
 
 def test_sequential_seeded_chain_matches_oracle():
