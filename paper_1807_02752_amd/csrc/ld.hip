@@ -1193,8 +1193,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     float* qb0 = fsm;                // W, dense q row (ping)
     float* qb1 = qb0 + W;            // W, dense q row (pong)
     float* Vp = qb1 + W;             // W + 4: V row with two zero columns on each side
-    float* mb0 = Vp + W + 4;         // W, M_1 row of even v
-    float* mb1 = mb0 + W;            // W, M_1 row of odd v
+    float* mb0 = Vp + W + 4;         // W + 1, M_1 row of even v (entry W stays 0)
+    float* mb1 = mb0 + W + 1;        // W + 1, M_1 row of odd v (entry W stays 0)
     const double* tf = d.tab + (int64_t)b * 6 * H;
     const double* tvpy = tf + 2 * H;
     const double* tvpx = tf + 3 * H;
@@ -1213,7 +1213,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         const double vx = tvpx[r], vy = tvpy[r];
         for (int i = lane; i < cnt; i += kWave) qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx, vy, inv_sg2, sq);
     }
-    for (int i = t; i < 5 * W + 4; i += kBlock) fsm[i] = 0.0f;
+    for (int i = t; i < 5 * W + 6; i += kBlock) fsm[i] = 0.0f;
     float ring[NC][9];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
@@ -1228,7 +1228,6 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         ee[k] = 0.0;
         live[k] = i < W2 && (cand_mask == nullptr || cand_mask[(int64_t)b * W2 + i] != 0);
     }
-    const double Wd = (double)W;
     __syncthreads();
 
     auto scatter = [&](int r, float* qb) {
@@ -1247,18 +1246,19 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
             if (u < W) { ring[k][S] = qb[u]; qb[u] = 0.0f; }
         }
     };
-    // the track of every live candidate moves to row w and adds M_1(col, w)
+    // the track of every live candidate moves to row w and adds M_1(col, w); a track outside
+    // the image (or a dead candidate) reads the zero entry W (ee is never -0, so adding +0
+    // leaves it unchanged).  The tracks are finite (A_v, B_v are finite on the swept rows);
+    // the conversion saturates, so the unsigned compare also rejects x < 0 and huge x.
     auto candidates = [&](int w, const float* m1row) {
         const bool upd = w < v_max;
         const double A = upd ? tA[w] : 0.0, Bc = upd ? tB[w] : 1.0;   // fma(1, u, 0) = u
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             uu[k] = fma(Bc, uu[k], A);
-            const double x = uu[k] + 0.5;
-            const bool in = live[k] && x >= 0.0 && x < Wd;
-            const int col = in ? (int)floor(x) : 0;
-            const float m = m1row[col];
-            ee[k] += in ? (double)m : 0.0;    // ee is never -0, so adding +0 leaves it unchanged
+            const int c = (int)floor(uu[k] + 0.5);
+            const bool in = live[k] && (unsigned)c < (unsigned)W;
+            ee[k] += (double)m1row[in ? c : W];
         }
     };
     // rows v_max .. v_max-3 enter slots 0, 8, 7, 6; rows below the image stay zero
@@ -1962,7 +1962,7 @@ size_t vpx_fit_lds(const Dev& d) {
     return sizeof(int) * (3 * WP + (size_t)d.H) + sizeof(uint32_t) * (size_t)vpx_walk_words_dev(d.W2);
 }
 
-size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 4); }
+size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 6); }
 
 // Raise a kernel's dynamic LDS limit once per size (later launches, including those recorded
 // into a captured graph, issue nothing but the launch).
