@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* dis
                 const uint64_t act = __ballot(valid);
                 if (act) {
                     const int leader = __ffsll((unsigned long long)act) - 1;
-                    const int b0 = __shfl(bin, leader, kWave);
+                    const int b0 = __builtin_amdgcn_readlane(bin, leader);   // uniform: no LDS round trip
                     const bool same = valid && bin == b0;
                     const uint64_t m = __ballot(same);
                     if (lane == leader) atomicAdd(&hist[(g + r) * D1 + b0], __popcll(m));
