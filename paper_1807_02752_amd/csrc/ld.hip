@@ -928,8 +928,12 @@ __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int*
     }
 }
 
-template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d) {
+// NRC: the run count NR of the interleaved rows as a compile-time constant (>= nwords + 2,
+// so the LDS offsets of the window below become immediates), or 0 for nwords + 2 at run time.
+// Six waves per SIMD (80 VGPRs, a few spilled) let four 320-thread frames share a CU, so a
+// 1024-frame batch runs in one round.
+template <int MAXT, int NRC>
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void k_vpx_fit(Dev d) {
     extern __shared__ unsigned char smem[];
     __shared__ int64_t rv[kMaxWaves];
     __shared__ int ri[kMaxWaves];
@@ -946,7 +950,7 @@ __global__ __launch_bounds__(MAXT) void k_vpx_fit(Dev d) {
     // DP rows and the band histogram are stored run-interleaved, column c at
     // (c mod 8) * NR + c / 8 + 1, so that the lanes of a wave (one run of 8 columns each)
     // touch consecutive words; runs -1 and nruns are padding (kBig).
-    const int NR = nwords + 2;
+    const int NR = NRC > 0 ? NRC : nwords + 2;
     const int WP = kDpRun * NR;
     int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved
     int* Sa = hist + WP;                 // E << 4
@@ -1957,8 +1961,17 @@ int vpx_fit_threads(const Dev& d) {
     return std::min(1024, std::max(64, (runs + 63) / 64 * 64));
 }
 
+// the compile-time run count k_vpx_fit<512, NRC> uses for this width (0: none fits)
+int vpx_fit_nrc(const Dev& d) {
+    const int nr = (d.W2 + kDpRun - 1) / kDpRun + 2;
+    for (int c : {64, 128, 256, 320, 512})
+        if (nr <= c) return c;
+    return 0;
+}
+
 size_t vpx_fit_lds(const Dev& d) {
-    const size_t WP = (size_t)kDpRun * ((d.W2 + kDpRun - 1) / kDpRun + 2);
+    const int nrc = vpx_fit_nrc(d);
+    const size_t WP = (size_t)kDpRun * (nrc > 0 ? nrc : (d.W2 + kDpRun - 1) / kDpRun + 2);
     return sizeof(int) * (3 * WP + (size_t)d.H) + sizeof(uint32_t) * (size_t)vpx_walk_words_dev(d.W2);
 }
 
@@ -2072,12 +2085,22 @@ ld_status run_vpx_dp(ld_frame f, const Dev& d, hipStream_t st) {
     const size_t l4 = vpx_fit_lds(d);
     const int nt4 = vpx_fit_threads(d);
     ProfScope ps(f, 3, st);
+    const int nrc = vpx_fit_nrc(d);
+    auto launch = [&](auto kernel) {
+        allow_lds(kernel, l4);
+        hipLaunchKernelGGL(kernel, dim3(f->active), dim3(nt4), l4, st, d);
+    };
     if (nt4 <= 512) {
-        allow_lds(k_vpx_fit<512>, l4);
-        hipLaunchKernelGGL(k_vpx_fit<512>, dim3(f->active), dim3(nt4), l4, st, d);
+        switch (nrc) {
+            case 64: launch(k_vpx_fit<512, 64>); break;
+            case 128: launch(k_vpx_fit<512, 128>); break;
+            case 256: launch(k_vpx_fit<512, 256>); break;
+            case 320: launch(k_vpx_fit<512, 320>); break;
+            case 512: launch(k_vpx_fit<512, 512>); break;
+            default: launch(k_vpx_fit<512, 0>); break;
+        }
     } else {
-        allow_lds(k_vpx_fit<1024>, l4);
-        hipLaunchKernelGGL(k_vpx_fit<1024>, dim3(f->active), dim3(nt4), l4, st, d);
+        launch(k_vpx_fit<1024, 0>);
     }
     return launch_ok();
 }
