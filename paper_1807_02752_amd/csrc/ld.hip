@@ -696,9 +696,9 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 // vote of every road edge (Eq. sparse_vpx_estimation with the gradient read as the edge
 // slope).  One wave covers 256 columns x kEdgeRows rows of one frame, four consecutive
 // columns per lane: each lane slides a 3-row window of six grey bytes (columns ub-1 .. ub+4)
-// down its columns, loading one new row per step, with the next row's raw disparities in
-// flight.  The road test is an integer compare against the row's raw interval.  A row's
-// edges are appended to its bucket with one atomic per wave.
+// down its columns with the grey row two steps ahead and the raw disparities of the next row
+// in flight.  The road test is an integer compare against the row's raw interval.  A row's
+// edges are appended to its bucket with one atomic per wave, written one step later.
 // Pixels outside the frame are never read for a result: the gradient is taken only at
 // 1 <= u <= W-2 and 1 <= v <= H-2, so the loads clamp their row and column into the frame
 // instead of masking (lanes whose six columns are all inside take the branch-free path).
@@ -735,7 +735,8 @@ __device__ __forceinline__ int vote_bin(double tt, int gy, int gx, int u, int ha
 
 template <int FMT>
 __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
-                                               int64_t dpitch) {
+                                               int64_t dpitch, const uint32_t* __restrict__ rbound,
+                                               const double* __restrict__ tab) {
     const int b = blockIdx.z, vb = blockIdx.y * kEdgeRows, lane = threadIdx.x;
     if (frame_masked(d, b)) return;
     const int ub = (blockIdx.x * kQT + lane) * 4;
@@ -744,25 +745,40 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
     if (fi.flags & LD_FLAG_NOROAD) return;
     const int vs = max(vb, fi.v_h), ve = min(vb + kEdgeRows - 1, H - 1);
     if (vs > ve) return;
-    const double* tvpy = d.tab + (int64_t)b * 6 * H + 2 * H;
-    const uint32_t* rb = d.rbound + (int64_t)b * H * 2;
+    const double* tvpy = tab + (int64_t)b * 6 * H + 2 * H;      // read only here (scalar loads)
+    const uint32_t* rb = rbound + (int64_t)b * H * 2;
     const int t2 = d.P.edge_t * d.P.edge_t;
     const bool inner = ub >= 1 && ub + 4 <= W - 1;
     const uint8_t* gbase = grey + (int64_t)b * H * gpitch;
     const uint8_t* dbase = disp + (int64_t)b * H * dpitch;
-    auto load_row = [&](int v, int* x) {     // x[0] = column ub-1 .. x[5] = ub+4
+    // a grey row's six bytes (columns ub-1 .. ub+4) stay packed, four in lo and two in hi,
+    // until the step that uses them, so a row loaded ahead is not waited for early
+    struct Row6 { uint32_t lo, hi; };
+    auto load_row = [&](int v) -> Row6 {
         const uint8_t* g = gbase + (int64_t)min(max(v, 0), H - 1) * gpitch;
+        Row6 r;
         if (inner) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) x[k] = g[ub - 1 + k];
+            __builtin_memcpy(&r.lo, g + ub - 1, 4);
+            uint16_t h;
+            __builtin_memcpy(&h, g + ub + 3, 2);
+            r.hi = h;
         } else {
+            r.lo = 0u; r.hi = 0u;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) x[k] = g[min(max(ub - 1 + k, 0), W - 1)];
+            for (int k = 0; k < 4; ++k) r.lo |= (uint32_t)g[min(max(ub - 1 + k, 0), W - 1)] << (8 * k);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) r.hi |= (uint32_t)g[min(max(ub + 3 + k, 0), W - 1)] << (8 * k);
         }
+        return r;
     };
-    int xa[6], xm[6], xc[6];
-    load_row(vs - 1, xa);
-    load_row(vs, xm);
+    auto unpack = [](const Row6& r, int* x) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = (int)((r.lo >> (8 * k)) & 255u);
+        x[4] = (int)(r.hi & 255u);
+        x[5] = (int)((r.hi >> 8) & 255u);
+    };
+    // rows v-1, v, v+1 of the current step and v+2 in flight
+    Row6 ga = load_row(vs - 1), gm = load_row(vs), gc = load_row(vs + 1);
     uint32_t rc[4], rn[4];
     auto load_raw = [&](int v, uint32_t* r) {
         const uint8_t* dr = dbase + (int64_t)min(v, ve) * dpitch;
@@ -775,12 +791,44 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
         }
     };
     load_raw(vs, rc);
+    uint32_t lo = rb[2 * vs], hi = rb[2 * vs + 1];      // road interval and V_py of the current row
+    double vpy = tvpy[vs];
+    // A row's edges are written one step later: its slot atomic is issued at the end of its
+    // step, and its result is waited for only after the next step's loads have been issued
+    // (memory results return in order, so an earlier wait would also wait for those loads).
+    int p_v = -1, p_tot = 0, p_base = 0;
+    uint32_t p_rec[4] = {0u, 0u, 0u, 0u}, p_mask = 0;
+    int p_bin[4] = {-1, -1, -1, -1};
+    uint64_t p_bal[4] = {0, 0, 0, 0};
+    auto flush = [&]() {
+        if (p_tot > 0) {
+            int off = __builtin_amdgcn_readlane(p_base, 0);
+            ld_edge* out = d.edges + ((int64_t)b * H + p_v) * W;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (p_mask & (1u << k)) {
+                    ld_edge e;
+                    e.u = (int16_t)(ub + k); e.gx = (int16_t)(p_rec[k] & 0xffffu); e.gy = (int16_t)(p_rec[k] >> 16);
+                    e.bin = (int16_t)p_bin[k];
+                    out[off + __popcll(p_bal[k] & lanes_below())] = e;
+                }
+                off += __popcll(p_bal[k]);
+            }
+        }
+    };
     for (int v = vs; v <= ve; ++v) {
-        load_row(v + 1, xc);
+        const Row6 gn = load_row(v + 2);
         load_raw(v + 1, rn);
+        const int vn = min(v + 1, ve);
+        const uint32_t lo_n = rb[2 * vn], hi_n = rb[2 * vn + 1];
+        const double vpy_n = tvpy[vn];
+        flush();
+        int xa[6], xm[6], xc[6];
+        unpack(ga, xa);
+        unpack(gm, xm);
+        unpack(gc, xc);
         const bool vin = v >= 1 && v <= H - 2;
-        const uint32_t lo = rb[2 * v], hi = rb[2 * v + 1];
-        const double tt = (double)v - tvpy[v];
+        const double tt = (double)v - vpy;
         uint32_t rec[4];
         int binv[4];
         uint64_t bal[4];
@@ -802,27 +850,18 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
             bal[k] = __ballot(edge);
         }
         const int tot = __popcll(bal[0]) + __popcll(bal[1]) + __popcll(bal[2]) + __popcll(bal[3]);
-        if (tot > 0) {
-            int base = 0;
-            if (lane == 0) base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], tot);
-            int off = __shfl(base, 0, kWave);
-            ld_edge* out = d.edges + ((int64_t)b * H + v) * W;
+        p_v = v;
+        p_tot = tot;
+        p_mask = emask;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (emask & (1u << k)) {
-                    ld_edge e;
-                    e.u = (int16_t)(ub + k); e.gx = (int16_t)(rec[k] & 0xffffu); e.gy = (int16_t)(rec[k] >> 16);
-                    e.bin = (int16_t)binv[k];
-                    out[off + __popcll(bal[k] & lanes_below())] = e;
-                }
-                off += __popcll(bal[k]);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) { xa[k] = xm[k]; xm[k] = xc[k]; }
+        for (int k = 0; k < 4; ++k) { p_rec[k] = rec[k]; p_bin[k] = binv[k]; p_bal[k] = bal[k]; }
+        if (tot > 0 && lane == 0) p_base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], tot);
+        ga = gm; gm = gc; gc = gn;
 #pragma unroll
         for (int k = 0; k < 4; ++k) rc[k] = rn[k];
+        lo = lo_n; hi = hi_n; vpy = vpy_n;
     }
+    flush();
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2074,9 +2113,14 @@ ld_status run_edges(ld_frame f, const uint8_t* grey, int64_t gp, const void* dis
     dim3 g3((d.W + 4 * kQT - 1) / (4 * kQT), (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
     ProfScope ps(f, 2, st);
-    if (d.fmt == LD_DISP_U8) hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
-    else if (d.fmt == LD_DISP_F32) hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
-    else hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt);
+    const uint32_t* rbd = d.rbound;
+    const double* tabd = d.tab;
+    if (d.fmt == LD_DISP_U8)
+        hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
+    else if (d.fmt == LD_DISP_F32)
+        hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
+    else
+        hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
     return launch_ok();
 }
 
