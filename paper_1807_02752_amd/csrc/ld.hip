@@ -703,6 +703,7 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 // 1 <= u <= W-2 and 1 <= v <= H-2, so the loads clamp their row and column into the frame
 // instead of masking (lanes whose six columns are all inside take the branch-free path).
 constexpr int kEdgeRows = 16;
+static_assert(sizeof(ld_edge) == 8, "an edge record is written as one 8-byte store");
 constexpr int kQT = 64;                 // threads per workgroup (one wave), 4 columns each
 template <int FMT>
 __device__ __forceinline__ uint32_t disp_raw(const uint8_t* row, int u) {
@@ -794,23 +795,24 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
     uint32_t lo = rb[2 * vs], hi = rb[2 * vs + 1];      // road interval and V_py of the current row
     double vpy = tvpy[vs];
     // A row's edges are written one step later: its slot atomic is issued at the end of its
-    // step, and its result is waited for only after the next step's loads have been issued
-    // (memory results return in order, so an earlier wait would also wait for those loads).
+    // step and its records are stored at the end of the next step, after that step's work, so
+    // no wait for a store or an atomic result comes between a step's loads and its use of the
+    // previous step's loads (memory operations complete in order).
     int p_v = -1, p_tot = 0, p_base = 0;
     uint32_t p_rec[4] = {0u, 0u, 0u, 0u}, p_mask = 0;
     int p_bin[4] = {-1, -1, -1, -1};
     uint64_t p_bal[4] = {0, 0, 0, 0};
+    __builtin_amdgcn_s_waitcnt(0x0070);   // the prologue's loads (vector and scalar), so no path enters the loop with loads pending
     auto flush = [&]() {
         if (p_tot > 0) {
             int off = __builtin_amdgcn_readlane(p_base, 0);
             ld_edge* out = d.edges + ((int64_t)b * H + p_v) * W;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (p_mask & (1u << k)) {
-                    ld_edge e;
-                    e.u = (int16_t)(ub + k); e.gx = (int16_t)(p_rec[k] & 0xffffu); e.gy = (int16_t)(p_rec[k] >> 16);
-                    e.bin = (int16_t)p_bin[k];
-                    out[off + __popcll(p_bal[k] & lanes_below())] = e;
+                if (p_mask & (1u << k)) {   // one 8-byte store: (u, gx) and (gy, vote column)
+                    const uint2 e = make_uint2((uint32_t)(uint16_t)(ub + k) | (p_rec[k] << 16),
+                                               (p_rec[k] >> 16) | ((uint32_t)(uint16_t)p_bin[k] << 16));
+                    reinterpret_cast<uint2*>(out)[off + __popcll(p_bal[k] & lanes_below())] = e;
                 }
                 off += __popcll(p_bal[k]);
             }
@@ -822,7 +824,6 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
         const int vn = min(v + 1, ve);
         const uint32_t lo_n = rb[2 * vn], hi_n = rb[2 * vn + 1];
         const double vpy_n = tvpy[vn];
-        flush();
         int xa[6], xm[6], xc[6];
         unpack(ga, xa);
         unpack(gm, xm);
@@ -850,12 +851,16 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
             bal[k] = __ballot(edge);
         }
         const int tot = __popcll(bal[0]) + __popcll(bal[1]) + __popcll(bal[2]) + __popcll(bal[3]);
+        flush();                     // the previous row's records, after this row's work
         p_v = v;
         p_tot = tot;
         p_mask = emask;
 #pragma unroll
         for (int k = 0; k < 4; ++k) { p_rec[k] = rec[k]; p_bin[k] = binv[k]; p_bal[k] = bal[k]; }
         if (tot > 0 && lane == 0) p_base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], tot);
+        // this step's loads are complete before the next step on every path (vmcnt 0, the
+        // other counters untouched), so the next step's work never waits for its own loads
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         ga = gm; gm = gc; gc = gn;
 #pragma unroll
         for (int k = 0; k < 4; ++k) rc[k] = rn[k];
