@@ -1284,6 +1284,22 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
             for (int i = t; i < cnt; i += kBlock) qb[edges[(int64_t)r * W + i].u] = qbuf[(int64_t)r * W + i];
         }
     };
+    // the next row to scatter: its count and each thread's first edge are loaded a step ahead
+    // (from a clamped, always valid index; the count masks them when they are used)
+    int nx_r = -1, nx_cnt = 0, nx_u = 0;
+    float nx_q = 0.0f;
+    auto prefetch = [&](int r) {
+        const int rr = min(max(r, 0), v_max), i = min(t, W - 1);
+        nx_r = r;
+        nx_cnt = (r >= v_h && r <= v_max) ? rowcnt[rr] : 0;
+        nx_u = edges[(int64_t)rr * W + i].u;
+        nx_q = qbuf[(int64_t)rr * W + i];
+    };
+    auto scatter_next = [&](float* qb) {
+        if (t < nx_cnt) qb[nx_u] = nx_q;
+        for (int i = t + kBlock; i < nx_cnt; i += kBlock)
+            qb[edges[(int64_t)nx_r * W + i].u] = qbuf[(int64_t)nx_r * W + i];
+    };
     // slot S of the ring takes the newest row; reads and re-zeroes the owned columns of qb
     auto push = [&](auto Sc, float* qb) {
         constexpr int S = decltype(Sc)::value;
@@ -1298,9 +1314,16 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     // the image (or a dead candidate) reads the zero entry W (ee is never -0, so adding +0
     // leaves it unchanged).  The tracks are finite (A_v, B_v are finite on the swept rows);
     // the conversion saturates, so the unsigned compare also rejects x < 0 and huge x.
-    auto candidates = [&](int w, const float* m1row) {
+    // A_w, B_w are loaded one step before their row's turn (fma(1, u, 0) = u for w = v_max).
+    double cA = 0.0, cB = 1.0;
+    auto coef = [&](int w) {
         const bool upd = w < v_max;
-        const double A = upd ? tA[w] : 0.0, Bc = upd ? tB[w] : 1.0;   // fma(1, u, 0) = u
+        cA = upd ? tA[w] : 0.0;
+        cB = upd ? tB[w] : 1.0;
+    };
+    auto candidates = [&](int w, const float* m1row) {
+        const double A = cA, Bc = cB;
+        (void)w;
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             uu[k] = fma(Bc, uu[k], A);
@@ -1314,13 +1337,15 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     scatter(v_max - 1, qb1); __syncthreads(); push(IntC<8>{}, qb1);
     scatter(v_max - 2, qb0); __syncthreads(); push(IntC<7>{}, qb0);
     scatter(v_max - 3, qb1); __syncthreads(); push(IntC<6>{}, qb1);
+    prefetch(v_max - 4);
     int v = v_max;
     // one row: newest ring slot S holds row v-4, slot (S + j) % 9 row v-4+j
     auto step = [&](auto Sc) -> bool {
         constexpr int S = decltype(Sc)::value;
         if (v < v_end) return false;
         float* qb = ((v_max - v) & 1) ? qb1 : qb0;
-        scatter(v - 4, qb);
+        scatter_next(qb);              // row v - 4
+        prefetch(v - 5);
         __syncthreads();
         push(Sc, qb);
 #pragma unroll
@@ -1353,6 +1378,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
             }
         }
         if (v < v_max) candidates(v + 1, ((v + 1) & 1) ? mb1 : mb0);
+        coef(v);                       // for this row's candidates in the next step
         --v;
         return true;
     };
