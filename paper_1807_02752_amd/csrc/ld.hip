@@ -564,9 +564,20 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
             const int v = t + k * nt;
             if (v < H) {
                 int best = Ec[v], bt = 0;
-                for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
-                    const int c = Ec[v + tau] + lam * tau;
-                    if (c < best) { best = c; bt = tau; }
+                if (tau_max <= 8) {   // every candidate read at once (clamped), then the same strict-< order
+                    int e[9];
+#pragma unroll
+                    for (int j = 1; j <= 8; ++j) e[j] = Ec[min(v + j, H - 1)];
+#pragma unroll
+                    for (int tau = 1; tau <= 8; ++tau) {
+                        const int c = e[tau] + lam * tau;
+                        if (tau <= tau_max && v + tau <= H - 1 && c < best) { best = c; bt = tau; }
+                    }
+                } else {
+                    for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
+                        const int c = Ec[v + tau] + lam * tau;
+                        if (c < best) { best = c; bt = tau; }
+                    }
                 }
                 En[v] = -curm[k] + best;
                 back[(int64_t)dd * H + v] = (uint8_t)bt;
