@@ -1605,8 +1605,9 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 // takes the neighbours' values from lanes l-2 .. l+2 by DPP wave shifts, so a row needs no
 // barrier; the band deltas of a row go through LDS atomics, from the road rows' vote columns
 // staged in LDS before the sweep; the backtrace (the rank of tau, 4 bits per column,
-// 128 B per row) goes to the frame's backtrace buffer and is walked through LDS 32 rows at a
-// time.  Needs W >= 128 (the buffer holds W bytes per row); narrower frames use the full search.
+// 128 B per row) goes to the frame's backtrace buffer and is walked 32 rows at a time from
+// registers.  Needs W >= 128 (the buffer holds W bytes per row); narrower frames use the full
+// search.
 constexpr int kWalkChunk = 32;
 
 __device__ __forceinline__ int shfl_i(int x, int src) { return __shfl(x, src, kWave); }
@@ -1633,7 +1634,6 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     int* path = cntL + H;                                     // H + 1 (the last: touch flag)
     int* roff = path + H + 1;                                 // R + 1 <= H + 1
     uint8_t* wb = reinterpret_cast<uint8_t*>(roff + H + 1);               // stage_cap bytes
-    uint16_t* stage = reinterpret_cast<uint16_t*>(wb);                    // kWalkChunk x 64, after the sweep
     uint16_t* back = reinterpret_cast<uint16_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 2;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
     for (int v = l; v < H; v += kWave) cntL[v] = d.rowcnt[(int64_t)b * H + v];
@@ -1660,22 +1660,30 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     auto woff = [&](int c) -> uint8_t { return (c >= lo && c <= hi) ? (uint8_t)(c - lo) : (uint8_t)255; };
     int nv = 0;
     if (staged) {
-        for (int v0 = v_h; v0 <= v_max; v0 += 16) {
-            int c2[16][2];
+        // the next group of 16 rows is loaded while the current one is written to LDS
+        int c2[16][2];
+        auto load_group = [&](int v0, int (&c)[16][2]) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int v = v0 + k, n = v <= v_max ? cntL[v] : 0;
-                c2[k][0] = l < n ? fe[(int64_t)v * d.W + l].bin : -1;
-                c2[k][1] = l + kWave < n ? fe[(int64_t)v * d.W + l + kWave].bin : -1;
+                c[k][0] = l < n ? fe[(int64_t)v * d.W + l].bin : -1;
+                c[k][1] = l + kWave < n ? fe[(int64_t)v * d.W + l + kWave].bin : -1;
             }
+        };
+        load_group(v_h, c2);
+        for (int v0 = v_h; v0 <= v_max; v0 += 16) {
+            int cg[16][2];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) { cg[k][0] = c2[k][0]; cg[k][1] = c2[k][1]; }
+            if (v0 + 16 <= v_max) load_group(v0 + 16, c2);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int v = v0 + k;
                 if (v > v_max) break;
                 const int n = cntL[v], o = roff[v - v_h];
-                nv += (c2[k][0] >= 0 ? 1 : 0) + (c2[k][1] >= 0 ? 1 : 0);
-                if (l < n) wb[o + l] = woff(c2[k][0]);
-                if (l + kWave < n) wb[o + l + kWave] = woff(c2[k][1]);
+                nv += (cg[k][0] >= 0 ? 1 : 0) + (cg[k][1] >= 0 ? 1 : 0);
+                if (l < n) wb[o + l] = woff(cg[k][0]);
+                if (l + kWave < n) wb[o + l + kWave] = woff(cg[k][1]);
                 for (int i0 = l + 2 * kWave; i0 < n; i0 += 8 * kWave) {   // long rows: 8 loads in flight
                     int cc[8];
 #pragma unroll
@@ -1833,23 +1841,39 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         if (4 * l + j < win && (int64_t)(S[j] >> 4) < bv) { bv = S[j] >> 4; bc = 4 * l + j; }
     wave_argmin_i64(bv, bc);
     __threadfence_block();   // the backtrace stores are complete before the wave reads them back
+    // Walk: the backtrace words of kWalkChunk rows in registers (lane l holds columns
+    // 4l .. 4l+3 of each row) with the next chunk in flight; the column is wave-uniform, so a
+    // step is a readlane and a few scalar operations.  Lane r keeps the path of row v0 + r.
     int c = bc, touch = 0;
-    for (int v0 = v_h; v0 <= v_max; v0 += kWalkChunk) {
-        const int rows = min(kWalkChunk, v_max - v0);          // rows with a backtrace entry
-        for (int r = 0; r < rows; ++r) stage[r * kWave + l] = back[(int64_t)(v0 - v_h + r) * kWave + l];
-        if (l == 0) {
-            const int last = min(v0 + kWalkChunk - 1, v_max);
-            for (int v = v0; v <= last; ++v) {
-                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
-                path[v] = lo + c;
-                if (v < v_max) c += rank_to_tau((int)((stage[(v - v0) * kWave + (c >> 2)] >> (4 * (c & 3))) & 15u));
-            }
-            path[H] = touch;
+    uint32_t bk[kWalkChunk], bn[kWalkChunk];
+    auto load_chunk = [&](int v0, uint32_t (&dst)[kWalkChunk]) {
+#pragma unroll
+        for (int r = 0; r < kWalkChunk; ++r) {
+            const int v = min(v0 + r, v_max - 1);          // rows v < v_max hold an entry
+            dst[r] = back[(int64_t)max(v - v_h, 0) * kWave + l];
         }
-        c = __shfl(c, 0, kWave);
+    };
+    load_chunk(v_h, bk);
+    for (int v0 = v_h; v0 <= v_max; v0 += kWalkChunk) {
+        load_chunk(v0 + kWalkChunk, bn);          // clamped: always a full chunk of loads
+        int pv = 0;
+#pragma unroll
+        for (int r = 0; r < kWalkChunk; ++r) {
+            const int v = v0 + r;
+            if (v <= v_max) {
+                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
+                if (l == r) pv = lo + c;
+                if (v < v_max) {
+                    const uint32_t word = __builtin_amdgcn_readlane(bk[r], c >> 2);
+                    c += rank_to_tau((int)((word >> (4 * (c & 3))) & 15u));
+                }
+            }
+        }
+        if (l < kWalkChunk && v0 + l <= v_max) path[v0 + l] = pv;
+#pragma unroll
+        for (int r = 0; r < kWalkChunk; ++r) bk[r] = bn[r];
     }
     nv = wave_sum_i32(nv);
-    touch = path[H];
     if (touch) {
         if (l == 0) pr[1] |= kFbPlainVpx | kFbTouch;
         return;
