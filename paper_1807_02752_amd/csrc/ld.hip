@@ -1161,7 +1161,13 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
 // columns), V_px and the track tables.  One 128-thread workgroup per frame (the RANSAC's
 // registers allow many per CU).  Hypothesis 0: the caller's seed rows (plain search), or the
 // seed of the narrowed search for the frames that kept it (pruned = 1).
-__global__ __launch_bounds__(128) void k_vpx_ransac(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
+// Three waves per frame: the inlier counts of a round split the points over the waves, and
+// three 192-thread workgroups per CU still hold every frame of a 1024 batch at once.
+#ifndef LD_RANSAC_THREADS
+#define LD_RANSAC_THREADS 192
+#endif
+constexpr int kRansacThreads = LD_RANSAC_THREADS;
+__global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
                                                     const double* seed_gamma, int pruned, double* vp_out) {
     extern __shared__ unsigned char smem[];
     __shared__ RansacShared S;
@@ -2222,7 +2228,7 @@ ld_status run_vpx_ransac(ld_frame f, const uint64_t* sid, const int64_t* fidx, c
     const size_t l = sizeof(int) * 4 * (size_t)d.H + sizeof(uint32_t) * ((d.H + 31) / 32);
     allow_lds(k_vpx_ransac, l);
     ProfScope ps(f, 10, st);
-    hipLaunchKernelGGL(k_vpx_ransac, dim3(f->active), dim3(128), l, st, d, sid, fidx, seed_gamma, pruned, vp_out);
+    hipLaunchKernelGGL(k_vpx_ransac, dim3(f->active), dim3(kRansacThreads), l, st, d, sid, fidx, seed_gamma, pruned, vp_out);
     return launch_ok();
 }
 
