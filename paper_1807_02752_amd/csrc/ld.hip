@@ -1053,28 +1053,46 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
     for (int j = 0; j < kWin; ++j) K[j] = ((3 + j) & (kDpRun - 1)) * NR + ((3 + j) >> 3);
     const int sc0 = slope * c0;
     const bool full5 = tau_max == 5;
-    // band rows entering / leaving at the next DP row, prefetched one row ahead
-    int nadd[kBandPer], nrem[kBandPer];
+    // band rows entering / leaving at the next DP row: each thread's first edge of both rows is
+    // prefetched one row ahead (one register each keeps the kernel at 80 VGPRs); the edges past
+    // the first blockDim.x of a row (rare) are read when the row is applied
+    auto first_bin = [&](int r, bool in) -> int {
+        const int n = in ? cntL[r] : 0;
+        return t < n ? fedges[(int64_t)r * d.W + t].bin : -1;
+    };
+    auto rest_apply = [&](int r, bool in, int sign) {
+        const int n = in ? cntL[r] : 0;
+        for (int i = t + nt; i < n; i += nt) {
+            const int c = fedges[(int64_t)r * d.W + i].bin;
+            if (c >= 0) {
+                atomicAdd(&hist[ipos(c, NR)], sign);
+                nv += sign > 0 ? 1 : 0;
+            }
+        }
+    };
+    int nadd, nrem;
     {
         const int v = v_max - 1;
         const int ra = v - chi, rr = v + chi + 1;
-        band_load(fedges + (int64_t)max(ra, 0) * d.W, ra >= v_h ? cntL[ra] : 0, nadd);
-        band_load(fedges + (int64_t)min(rr, v_max) * d.W, rr <= v_max ? cntL[rr] : 0, nrem);
+        nadd = first_bin(max(ra, 0), ra >= v_h);
+        nrem = first_bin(min(rr, v_max), rr <= v_max);
     }
     int parity = 0;   // 0: read Sa, write Sb
     for (int v = v_max - 1; v >= v_h; --v) {
-        int cadd[kBandPer], crem[kBandPer];
-#pragma unroll
-        for (int k = 0; k < kBandPer; ++k) { cadd[k] = nadd[k]; crem[k] = nrem[k]; }
+        const int cadd = nadd, crem = nrem;
         if (v - 1 >= v_h) {
             const int ra = v - 1 - chi, rr = v + chi;
-            band_load(fedges + (int64_t)max(ra, 0) * d.W, ra >= v_h ? cntL[ra] : 0, nadd);
-            band_load(fedges + (int64_t)min(rr, v_max) * d.W, rr <= v_max ? cntL[rr] : 0, nrem);
+            nadd = first_bin(max(ra, 0), ra >= v_h);
+            nrem = first_bin(min(rr, v_max), rr <= v_max);
         }
-#pragma unroll
-        for (int k = 0; k < kBandPer; ++k) nv += cadd[k] >= 0 ? 1 : 0;
-        band_apply(cadd, 1, hist, NR);
-        band_apply(crem, -1, hist, NR);
+        nv += cadd >= 0 ? 1 : 0;
+        if (cadd >= 0) atomicAdd(&hist[ipos(cadd, NR)], 1);
+        if (crem >= 0) atomicAdd(&hist[ipos(crem, NR)], -1);
+        {
+            const int ra = v - chi, rr = v + chi + 1;
+            rest_apply(max(ra, 0), ra >= v_h, 1);
+            rest_apply(min(rr, v_max), rr <= v_max, -1);
+        }
         __syncthreads();
         if (c0 < W2) {
             const int* src = (parity ? Sb : Sa) + t;
