@@ -985,7 +985,7 @@ __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int*
 
 // NRC: the run count NR of the interleaved rows as a compile-time constant (>= nwords + 2,
 // so the LDS offsets of the window below become immediates), or 0 for nwords + 2 at run time.
-// Six waves per SIMD (80 VGPRs, a few spilled) let four 320-thread frames share a CU, so a
+// Six waves per SIMD (80 VGPRs) let four 320-thread frames share a CU, so a
 // 1024-frame batch runs in one round.
 template <int MAXT, int NRC>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void k_vpx_fit(Dev d) {
@@ -1007,7 +1007,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
     // touch consecutive words; runs -1 and nruns are padding (kBig).
     const int NR = NRC > 0 ? NRC : nwords + 2;
     const int WP = kDpRun * NR;
-    int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved
+    int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved, 16 x the band's votes
     int* Sa = hist + WP;                 // E << 4
     int* Sb = Sa + WP;
     uint32_t* win = reinterpret_cast<uint32_t*>(Sb + WP);   // kWalkRows x walk-window words
@@ -1032,26 +1032,22 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
             for (int k = 0; k < kBandPer; ++k) nv += bins[j][k] >= 0 ? 1 : 0;
-            band_apply(bins[j], 1, hist, NR);
+            band_apply(bins[j], 16, hist, NR);
         }
     }
     __syncthreads();
-    for (int c = t; c < W2; c += nt) Sa[ipos(c, NR)] = -hist[ipos(c, NR)] * 16;
+    for (int c = t; c < W2; c += nt) Sa[ipos(c, NR)] = -hist[ipos(c, NR)];
     __syncthreads();
     const int tau_max = d.P.tau_x_max;
     const int slope = 16 * d.P.lambda_x + 2;
     uint32_t* back = reinterpret_cast<uint32_t*>(d.back_x) + (int64_t)b * H * nwords;
     const int c0 = t * kDpRun;
-    // row-invariant per-thread constants: LDS positions of the window Sh(c0-5 .. c0+12) and
-    // of the own columns in both DP buffers, and the slope offsets slope * c of the window
+    // each thread's window Sh(c0-5 .. c0+12) of a DP row: window column c0 - 5 + j sits at int
+    // index t + K[j] (K uniform over the workgroup: K[j] = ((3 + j) mod 8) NR + (3 + j) div 8)
     constexpr int kWin = kDpRun + 10;
-    // window column c0 - 5 + j sits at int index t + K[j] of a DP row (K uniform over the
-    // workgroup: K[j] = ((3 + j) mod 8) NR + (3 + j) div 8), and its slope offset is
-    // slope * c0 + slope * (j - 5)
     int K[kWin];
 #pragma unroll
     for (int j = 0; j < kWin; ++j) K[j] = ((3 + j) & (kDpRun - 1)) * NR + ((3 + j) >> 3);
-    const int sc0 = slope * c0;
     const bool full5 = tau_max == 5;
     // band rows entering / leaving at the next DP row: each thread's first edge of both rows is
     // prefetched one row ahead (one register each keeps the kernel at 80 VGPRs); the edges past
@@ -1065,7 +1061,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
         for (int i = t + nt; i < n; i += nt) {
             const int c = fedges[(int64_t)r * d.W + i].bin;
             if (c >= 0) {
-                atomicAdd(&hist[ipos(c, NR)], sign);
+                atomicAdd(&hist[ipos(c, NR)], 16 * sign);
                 nv += sign > 0 ? 1 : 0;
             }
         }
@@ -1077,59 +1073,71 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
         nadd = first_bin(max(ra, 0), ra >= v_h);
         nrem = first_bin(min(rr, v_max), rr <= v_max);
     }
+    // bits of the backtrace word that belong to columns below W2
+    const uint32_t wmask = c0 + kDpRun <= W2 ? 0xFFFFFFFFu : (1u << (4 * max(W2 - c0, 0))) - 1u;
     int parity = 0;   // 0: read Sa, write Sb
-    for (int v = v_max - 1; v >= v_h; --v) {
-        const int cadd = nadd, crem = nrem;
-        if (v - 1 >= v_h) {
-            const int ra = v - 1 - chi, rr = v + chi;
-            nadd = first_bin(max(ra, 0), ra >= v_h);
-            nrem = first_bin(min(rr, v_max), rr <= v_max);
-        }
-        nv += cadd >= 0 ? 1 : 0;
-        if (cadd >= 0) atomicAdd(&hist[ipos(cadd, NR)], 1);
-        if (crem >= 0) atomicAdd(&hist[ipos(crem, NR)], -1);
-        {
-            const int ra = v - chi, rr = v + chi + 1;
-            rest_apply(max(ra, 0), ra >= v_h, 1);
-            rest_apply(min(rr, v_max), rr <= v_max, -1);
-        }
-        __syncthreads();
-        if (c0 < W2) {
-            const int* src = (parity ? Sb : Sa) + t;
-            int* dst = (parity ? Sa : Sb) + t;
-            int w[kWin], TL[kWin], TR[kWin];
-#pragma unroll
-            for (int j = 0; j < kWin; ++j) {
-                w[j] = src[K[j]];
-                const int off = sc0 + slope * (j - 5);
-                TL[j] = w[j] - off;              // key of tau < 0 minus the per-c constant
-                TR[j] = w[j] + off;              // key of tau > 0 plus the per-c constant
+    // The row recursion, instantiated once for the full window (tau_max = 5) and once for a
+    // narrower one, so the per-column minima carry no run-time test.  The per-c constant of
+    // the window minima cancels between the shifted terms and the result, so only the
+    // uniform offsets slope * (j - 5) and slope * k enter.
+    auto dp_rows = [&](auto full) {
+        constexpr bool kFull = decltype(full)::value;
+        for (int v = v_max - 1; v >= v_h; --v) {
+            const int cadd = nadd, crem = nrem;
+            if (v - 1 >= v_h) {
+                const int ra = v - 1 - chi, rr = v + chi;
+                nadd = first_bin(max(ra, 0), ra >= v_h);
+                nrem = first_bin(min(rr, v_max), rr <= v_max);
             }
-            uint32_t word = 0;
+            nv += cadd >= 0 ? 1 : 0;
+            if (cadd >= 0) atomicAdd(&hist[ipos(cadd, NR)], 16);
+            if (crem >= 0) atomicAdd(&hist[ipos(crem, NR)], -16);
+            {
+                const int ra = v - chi, rr = v + chi + 1;
+                rest_apply(max(ra, 0), ra >= v_h, 1);
+                rest_apply(min(rr, v_max), rr <= v_max, -1);
+            }
+            __syncthreads();
+            if (c0 < W2) {
+                const int* src = (parity ? Sb : Sa) + t;
+                int* dst = (parity ? Sa : Sb) + t;
+                const int* hs = hist + t;
+                int w[kWin], h[kDpRun], TL[kWin], TR[kWin];
 #pragma unroll
-            for (int k = 0; k < kDpRun; ++k) {
-                int lm, rm;
-                if (full5) {
-                    lm = min(min(min(TL[k], TL[k + 1]), min(TL[k + 2], TL[k + 3])), TL[k + 4]);
-                    rm = min(min(min(TR[k + 6], TR[k + 7]), min(TR[k + 8], TR[k + 9])), TR[k + 10]);
-                } else {
-                    lm = kBig; rm = kBig;
+                for (int j = 0; j < kWin; ++j) w[j] = src[K[j]];
 #pragma unroll
-                    for (int a = 1; a <= 5; ++a)
-                        if (a <= tau_max) { lm = min(lm, TL[k + 5 - a]); rm = min(rm, TR[k + 5 + a]); }
+                for (int k = 0; k < kDpRun; ++k) h[k] = hs[K[k + 5]];
+#pragma unroll
+                for (int j = 0; j < kWin; ++j) {
+                    TL[j] = w[j] - slope * (j - 5);     // tau < 0 terms, less slope * c
+                    TR[j] = w[j] + slope * (j - 5);     // tau > 0 terms, plus slope * c
                 }
-                const int cc = sc0 + slope * k;                      // slope * c
-                const int key = min(w[k + 5], min(lm + (cc - 1), rm - cc));
-                if (c0 + k < W2) {
-                    dst[K[k + 5]] = ((key >> 4) - hist[t + K[k + 5]]) * 16;
+                uint32_t word = 0;
+#pragma unroll
+                for (int k = 0; k < kDpRun; ++k) {
+                    int lm, rm;
+                    if constexpr (kFull) {
+                        lm = min(min(min(TL[k], TL[k + 1]), min(TL[k + 2], TL[k + 3])), TL[k + 4]);
+                        rm = min(min(min(TR[k + 6], TR[k + 7]), min(TR[k + 8], TR[k + 9])), TR[k + 10]);
+                    } else {
+                        lm = kBig; rm = kBig;
+#pragma unroll
+                        for (int a = 1; a <= 5; ++a)
+                            if (a <= tau_max) { lm = min(lm, TL[k + 5 - a]); rm = min(rm, TR[k + 5 + a]); }
+                    }
+                    const int key = min(w[k + 5], min(lm + (slope * k - 1), rm - slope * k));
+                    // (E_min - votes) << 4; columns past W2 keep the padding value
+                    dst[K[k + 5]] = c0 + k < W2 ? (key & -16) - h[k] : kBig;
                     word |= (uint32_t)(key & 15) << (4 * k);
                 }
+                back[(int64_t)v * nwords + t] = word & wmask;
             }
-            back[(int64_t)v * nwords + t] = word;
+            __syncthreads();
+            parity ^= 1;
         }
-        __syncthreads();
-        parity ^= 1;
-    }
+    };
+    if (full5) dp_rows(std::true_type{});
+    else dp_rows(std::false_type{});
     int* Sc = parity ? Sb : Sa;
     int64_t bvv = INT64_MAX;
     int bi = 0x7fffffff;
