@@ -510,6 +510,8 @@ __device__ void road_interval(int fmt, double f, double varpi, uint32_t& lo, uin
 constexpr int kVdRows = 4;                 // rows per thread in the v-disparity DP
 constexpr int kVdWalk = 32;                // DP steps of the backtrace staged in LDS per walk chunk
 constexpr int kVdWalkCols = 257;           // staged rows per step (covers kVdWalk steps of tau_max)
+constexpr int kVdPad = 8;                  // padding rows after each DP row
+constexpr int kVdPadKey = 0x3FFFFFF0;      // padding key: above any real key, and twice it fits int32
 
 __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* stream_ids, const int64_t* frame_idx,
                                                     double* beta_out) {
@@ -521,9 +523,11 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
     const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
     if (frame_masked(d, b)) return;
     const int H = d.H, D1 = d.D1, d_max = d.d_max;
+    // DP rows hold E << 4 (E <= 0, low 4 bits zero); the kVdPad entries past row H - 1 hold a
+    // key that loses to every real one
     int* E0 = reinterpret_cast<int*>(smem);
-    int* E1 = E0 + H;
-    int* PX = E1 + H;
+    int* E1 = E0 + H + kVdPad;
+    int* PX = E1 + H + kVdPad;
     int* PY = PX + D1;
     int* cur = PY + D1;
     int* cur2 = cur + D1;
@@ -535,9 +539,15 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
     const int tau_max = d.P.tau_y_max, lam = d.P.lambda_y;
 
     for (int v = t; v < H; v += nt) {
-        E0[v] = -myT[(int64_t)d_max * H + v];
+        E0[v] = -myT[(int64_t)d_max * H + v] * 16;
         d.rowcnt[(int64_t)b * H + v] = 0;
     }
+    if (t < kVdPad) { E0[H + t] = kVdPadKey; E1[H + t] = kVdPadKey; }
+    // step costs of the packed keys: 16 lambda tau + tau for an allowed jump, the padding key
+    // for tau > tau_max (so the key loses), for the window of up to 8 rows read at once
+    int addc[9];
+#pragma unroll
+    for (int tau = 1; tau <= 8; ++tau) addc[tau] = tau <= tau_max ? 16 * lam * tau + tau : kVdPadKey;
     // the column m_y(d, .) of the next DP step is loaded while the current one is computed
     int nxt[kVdRows];
 #pragma unroll
@@ -563,24 +573,27 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
         for (int k = 0; k < kVdRows; ++k) {
             const int v = t + k * nt;
             if (v < H) {
-                int best = Ec[v], bt = 0;
-                if (tau_max <= 8) {   // every candidate read at once (clamped), then the same strict-< order
+                if (tau_max <= 8) {
+                    // key of jump tau: (E(v + tau) + lambda tau) << 4 | tau; the minimum is the
+                    // smallest cost, and among equal costs the smallest tau (the strict-< scan
+                    // over tau = 0, 1, ...).  Rows past H - 1 read the padding.
                     int e[9];
 #pragma unroll
-                    for (int j = 1; j <= 8; ++j) e[j] = Ec[min(v + j, H - 1)];
+                    for (int j = 0; j <= 8; ++j) e[j] = Ec[v + j];
+                    int m = e[0];
 #pragma unroll
-                    for (int tau = 1; tau <= 8; ++tau) {
-                        const int c = e[tau] + lam * tau;
-                        if (tau <= tau_max && v + tau <= H - 1 && c < best) { best = c; bt = tau; }
-                    }
+                    for (int tau = 1; tau <= 8; ++tau) m = min(m, e[tau] + addc[tau]);
+                    En[v] = (m & -16) - curm[k] * 16;
+                    back[(int64_t)dd * H + v] = (uint8_t)(m & 15);
                 } else {
+                    int best = Ec[v] >> 4, bt = 0;
                     for (int tau = 1; tau <= tau_max && v + tau <= H - 1; ++tau) {
-                        const int c = Ec[v + tau] + lam * tau;
+                        const int c = (Ec[v + tau] >> 4) + lam * tau;
                         if (c < best) { best = c; bt = tau; }
                     }
+                    En[v] = (best - curm[k]) * 16;
+                    back[(int64_t)dd * H + v] = (uint8_t)bt;
                 }
-                En[v] = -curm[k] + best;
-                back[(int64_t)dd * H + v] = (uint8_t)bt;
             }
         }
         __syncthreads();
@@ -2089,7 +2102,7 @@ int vdisp_fit_threads(const Dev& d) {
 }
 
 size_t vdisp_fit_lds(const Dev& d) {
-    return sizeof(int) * (2 * (size_t)d.H + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32) +
+    return sizeof(int) * (2 * ((size_t)d.H + kVdPad) + 4 * (size_t)d.D1) + sizeof(uint32_t) * ((d.H + 31) / 32) +
            (size_t)kVdWalk * kVdWalkCols;
 }
 

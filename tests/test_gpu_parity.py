@@ -199,6 +199,20 @@ def test_ragged_sizes(W, H, d_max):
     compare_frame(out, 0, g, d, d_max)
 
 
+@pytest.mark.parametrize("tau_y,lam_y,tau_x,lam_x", [(0, 1, 5, 1), (3, 4, 3, 2), (8, 1, 1, 0), (12, 2, 4, 3)])
+def test_dp_windows_and_weights(tau_y, lam_y, tau_x, lam_x):
+    # jump windows and smoothness weights other than the defaults (6, 1, 5, 1): the v-disparity
+    # DP with its window up to 8 rows and beyond it, and the row DP with narrower windows
+    g, d, sc = synth.make_c2(1, 7)
+    kw = dict(tau_y_max=tau_y, lambda_y=lam_y, tau_x_max=tau_x, lambda_x=lam_x)
+    pg = _ld().params_default(**kw)
+    pr = oracle.default_params(**kw)
+    assert (pg.tau_y_max, pg.lambda_y, pg.tau_x_max, pg.lambda_x) == (pr.tau_y_max, pr.lambda_y, pr.tau_x_max,
+                                                                      pr.lambda_x) == (tau_y, lam_y, tau_x, lam_x)
+    out = run_gpu(g[None], d[None], 128, params=pg)
+    compare_frame(out, 0, g, d, 128, params=pr)
+
+
 @pytest.mark.parametrize("kind", ["all_invalid", "obstacle_only", "flat_image", "random"])
 def test_degenerate_frames(kind):
     g, d = synth.degenerate(kind)
