@@ -909,7 +909,7 @@ __global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64
 // minimum of a per-column term over a window, plus a per-c constant.  The rank (4 bits) is
 // the backtrace, eight columns per 32-bit word.
 constexpr int kDpRun = 8;
-constexpr int kWalkRows = 32;        // rows of the backtrace staged in LDS per walk chunk
+constexpr int kFitWalk = 16;         // rows of the backtrace per register chunk of the walk
 
 // The band edges of one row, up to kBandPer per thread (a row holds at most W edges and the
 // workgroup has at least W/4 threads).
@@ -932,12 +932,6 @@ __device__ __forceinline__ void band_apply(const int* bins, int sign, int* hist,
 #pragma unroll
     for (int k = 0; k < kBandPer; ++k)
         if (bins[k] >= 0) atomicAdd(&hist[ipos(bins[k], NR)], sign);
-}
-
-__host__ __device__ __forceinline__ int vpx_walk_words_dev(int W2) {
-    const int nwords = (W2 + kDpRun - 1) / kDpRun;
-    const int ww = 2 * (5 * kWalkRows) / kDpRun + 2;
-    return kWalkRows * (nwords < ww ? nwords : ww);
 }
 
 __device__ __forceinline__ int rank_to_tau(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
@@ -1006,7 +1000,6 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
     __shared__ int64_t rv[kMaxWaves];
     __shared__ int ri[kMaxWaves];
     __shared__ int red[kMaxWaves];
-    __shared__ int s_c;
     const int b = blockIdx.x, t = threadIdx.x, nt = blockDim.x;
     if (frame_masked(d, b)) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
@@ -1023,8 +1016,7 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
     int* hist = reinterpret_cast<int*>(smem);   // WP, interleaved, 16 x the band's votes
     int* Sa = hist + WP;                 // E << 4
     int* Sb = Sa + WP;
-    uint32_t* win = reinterpret_cast<uint32_t*>(Sb + WP);   // kWalkRows x walk-window words
-    int* cntL = reinterpret_cast<int*>(win + vpx_walk_words_dev(W2));   // per-row edge counts
+    int* cntL = Sb + WP;                 // per-row edge counts
     const ld_edge* fedges = d.edges + (int64_t)b * H * d.W;
     for (int v = t; v < H; v += nt) cntL[v] = d.rowcnt[(int64_t)b * H + v];
     for (int i = t; i < WP; i += nt) { hist[i] = 0; Sa[i] = kBig; Sb[i] = kBig; }
@@ -1159,34 +1151,46 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void 
         if (e < bvv) { bvv = e; bi = c; }
     }
     block_argmin_i64(bvv, bi, rv, ri);
-    // backtrace: stage kWalkRows rows of the packed backtrace around the path in LDS, then
-    // one thread follows the path through them
-    if (t == 0) s_c = bi;
-    __syncthreads();
-    const int span = 5 * kWalkRows;
-    for (int v0 = v_h; v0 <= v_max; v0 += kWalkRows) {
-        const int c = s_c;
-        const int rows = min(kWalkRows, v_max - v0);          // rows with a backtrace entry
-        const int w0 = max(0, (c - span) / kDpRun), w1 = min(nwords - 1, (c + span) / kDpRun);
-        const int ww = w1 - w0 + 1;
-        for (int i = t; i < rows * ww; i += nt) {
-            const int r = i / ww, k = i % ww;
-            win[i] = back[(int64_t)(v0 + r) * nwords + w0 + k];
-        }
-        __syncthreads();
-        if (t == 0) {
-            int cc = c;
-            const int last = min(v0 + kWalkRows - 1, v_max);
-            for (int v = v0; v <= last; ++v) {
-                d.mxpath[(int64_t)b * H + v] = cc;
-                if (v < v_max) {
-                    const uint32_t wd = win[(v - v0) * ww + cc / kDpRun - w0];
-                    cc += rank_to_tau((int)((wd >> (4 * (cc % kDpRun))) & 15u));
+    // backtrace, by wave 0: lane l holds word w0 + l of each of kFitWalk rows (64 words = 512
+    // columns), with the next chunk in flight; the column is wave-uniform, so a step is a
+    // readlane and a few scalar operations.  The path moves at most 5 columns a row, so from
+    // the start column c of a chunk it stays within c +- 5 kFitWalk over this chunk and within
+    // c +- 10 kFitWalk over the next, which the next chunk's words (centred on c) cover.
+    if (t < kWave) {
+        const int l = t;
+        int c = bi;
+        auto wbase = [&](int col) { return max(0, min((col >> 3) - 31, nwords - kWave)); };
+        uint32_t bk[kFitWalk], bn[kFitWalk];
+        auto load_chunk = [&](int v0, int w0, uint32_t (&dst)[kFitWalk]) {
+            const int wi = min(w0 + l, nwords - 1);
+#pragma unroll
+            for (int r = 0; r < kFitWalk; ++r) {
+                const int v = min(v0 + r, v_max - 1);          // rows v < v_max hold an entry
+                dst[r] = back[(int64_t)v * nwords + wi];
+            }
+        };
+        int wcur = wbase(c);
+        load_chunk(v_h, wcur, bk);
+        for (int v0 = v_h; v0 <= v_max; v0 += kFitWalk) {
+            const int wnext = wbase(c);
+            load_chunk(v0 + kFitWalk, wnext, bn);          // clamped rows: always a full chunk
+            int pv = 0;
+#pragma unroll
+            for (int r = 0; r < kFitWalk; ++r) {
+                const int v = v0 + r;
+                if (v <= v_max) {
+                    if (l == r) pv = c;
+                    if (v < v_max) {
+                        const uint32_t word = __builtin_amdgcn_readlane(bk[r], (c >> 3) - wcur);
+                        c += rank_to_tau((int)((word >> (4 * (c & 7))) & 15u));
+                    }
                 }
             }
-            s_c = cc;
+            if (l < kFitWalk && v0 + l <= v_max) d.mxpath[(int64_t)b * H + v0 + l] = pv;
+#pragma unroll
+            for (int r = 0; r < kFitWalk; ++r) bk[r] = bn[r];
+            wcur = wnext;
         }
-        __syncthreads();
     }
     nv = block_sum_i32(nv, red);
     if (t == 0) {
@@ -2122,7 +2126,7 @@ int vpx_fit_nrc(const Dev& d) {
 size_t vpx_fit_lds(const Dev& d) {
     const int nrc = vpx_fit_nrc(d);
     const size_t WP = (size_t)kDpRun * (nrc > 0 ? nrc : (d.W2 + kDpRun - 1) / kDpRun + 2);
-    return sizeof(int) * (3 * WP + (size_t)d.H) + sizeof(uint32_t) * (size_t)vpx_walk_words_dev(d.W2);
+    return sizeof(int) * (3 * WP + (size_t)d.H);
 }
 
 size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 6); }
