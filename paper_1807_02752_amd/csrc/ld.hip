@@ -992,10 +992,11 @@ __device__ void vpx_fit_tail(Dev& d, int b, FrameInfo fi, int* PX, int* PY, int*
 
 // NRC: the run count NR of the interleaved rows as a compile-time constant (>= nwords + 2,
 // so the LDS offsets of the window below become immediates), or 0 for nwords + 2 at run time.
-// Six waves per SIMD (80 VGPRs) let four 320-thread frames share a CU, so a
-// 1024-frame batch runs in one round.
+// Seven waves per SIMD (72 VGPRs, a few bytes spilled outside the row loop) leave room for
+// four 320-thread frames on every CU however their waves fall on its SIMDs, so a 1024-frame
+// batch runs in one round; at six waves per SIMD some CUs held only three of them.
 template <int MAXT, int NRC>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(6))) void k_vpx_fit(Dev d) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(7))) void k_vpx_fit(Dev d) {
     extern __shared__ unsigned char smem[];
     __shared__ int64_t rv[kMaxWaves];
     __shared__ int ri[kMaxWaves];
