@@ -1259,8 +1259,8 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
 // M_1 = Sobel-x of M_0 (Alg. "Lane position validation"), and the energy of every candidate
 // along its track (Eq. lane_energy, Eq. lane_visualisation).
 //
-// One workgroup per frame.  First q is computed for every road edge (one wave per row) into a
-// per-edge buffer.  Then the road rows are swept upwards: q row v-4 is scattered into a zeroed
+// One workgroup per frame.  First q is computed for every road edge (each wave a group of rows)
+// into a per-edge buffer.  Then the road rows are swept upwards: q row v-4 is scattered into a zeroed
 // LDS row, every thread pushes its NC columns into a 9-row register ring (rows v-4..v+4) and
 // forms V(x, v) = sum_y s_y C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0
 // outside the image; after a barrier the column owners form the row of
@@ -1316,11 +1316,31 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     float* qbuf = d.qbuf + (int64_t)b * H * W;
     const int32_t* rowcnt = d.rowcnt + (int64_t)b * H;
 
-    // q of every road edge, one wave per row
-    for (int r = v_h + wave; r <= v_max; r += kBlock / kWave) {
-        const int cnt = rowcnt[r];
-        const double vx = tvpx[r], vy = tvpy[r];
-        for (int i = lane; i < cnt; i += kWave) qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx, vy, inv_sg2, sq);
+    // q of every road edge: a wave takes kQRows rows at a time and loads two edge slots per
+    // lane (i = lane, lane + 64) of each, every load of the group issued before any q is
+    // formed (clamped to the row's W slots; the counts mask them); longer rows go on in a loop
+    constexpr int kQRows = 4;
+    for (int r0 = v_h + wave * kQRows; r0 <= v_max; r0 += (kBlock / kWave) * kQRows) {
+        int cnt[kQRows];
+        double vx[kQRows], vy[kQRows];
+        ld_edge e0[kQRows], e1[kQRows];
+#pragma unroll
+        for (int j = 0; j < kQRows; ++j) {
+            const int r = min(r0 + j, v_max);
+            cnt[j] = r0 + j <= v_max ? rowcnt[r] : 0;
+            vx[j] = tvpx[r];
+            vy[j] = tvpy[r];
+            e0[j] = edges[(int64_t)r * W + min(lane, W - 1)];
+            e1[j] = edges[(int64_t)r * W + min(lane + kWave, W - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < kQRows; ++j) {
+            const int r = r0 + j;
+            if (lane < cnt[j]) qbuf[(int64_t)r * W + lane] = edge_q(e0[j], r, vx[j], vy[j], inv_sg2, sq);
+            if (lane + kWave < cnt[j]) qbuf[(int64_t)r * W + lane + kWave] = edge_q(e1[j], r, vx[j], vy[j], inv_sg2, sq);
+            for (int i = lane + 2 * kWave; i < cnt[j]; i += kWave)
+                qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx[j], vy[j], inv_sg2, sq);
+        }
     }
     for (int i = t; i < 5 * W + 6; i += kBlock) fsm[i] = 0.0f;
     float ring[NC][9];
