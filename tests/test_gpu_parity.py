@@ -50,16 +50,20 @@ def run_gpu(greys, disps, d_max, params=None, stream_ids=None, frame_idx=None, s
         "lanes": ld.Detector.parse_lanes(lanes), "curves": curves.cpu().numpy(), "frames": [],
     }
     for b in range(B):
-        fr = {
-            "info": det.read(ld.LD_STATE_INFO, b), "my": det.read(ld.LD_STATE_MY_PATH, b),
-            "beta": det.read(ld.LD_STATE_BETA, b)[0], "gamma": det.read(ld.LD_STATE_GAMMA, b)[0],
-            "tables": det.read(ld.LD_STATE_TABLES, b).reshape(6, H), "rowcnt": det.read(ld.LD_STATE_ROWCOUNT, b),
-            "edges": det.read(ld.LD_STATE_EDGES, b).reshape(H, W), "mx": det.read(ld.LD_STATE_MX_PATH, b),
-            "energy": det.read(ld.LD_STATE_ENERGY, b), "trace": det.read(ld.LD_STATE_TRACE, b).reshape(2, 64, 3),
-        }
-        out["frames"].append(fr)
+        out["frames"].append(read_frame(det, b, H, W))
     det.close()
     return out
+
+
+def read_frame(det, b, H, W):
+    ld = _ld()
+    return {
+        "info": det.read(ld.LD_STATE_INFO, b), "my": det.read(ld.LD_STATE_MY_PATH, b),
+        "beta": det.read(ld.LD_STATE_BETA, b)[0], "gamma": det.read(ld.LD_STATE_GAMMA, b)[0],
+        "tables": det.read(ld.LD_STATE_TABLES, b).reshape(6, H), "rowcnt": det.read(ld.LD_STATE_ROWCOUNT, b),
+        "edges": det.read(ld.LD_STATE_EDGES, b).reshape(H, W), "mx": det.read(ld.LD_STATE_MX_PATH, b),
+        "energy": det.read(ld.LD_STATE_ENERGY, b), "trace": det.read(ld.LD_STATE_TRACE, b).reshape(2, 64, 3),
+    }
 
 
 def _fit_equal(g, r, degree):
@@ -103,8 +107,9 @@ def compare_frame(out, b, grey, disp, d_max, params=None, stream_id=0, frame_idx
     r = oracle.detect(grey, disp, d_max, params, stream_id=stream_id, frame_idx=b if frame_idx is None else frame_idx,
                       seed_gamma=seed_gamma)
     info = fr["info"]
-    # S1 histogram
-    assert np.array_equal(out["vdisp"][b], r.m_y)
+    # S1 histogram (outputs missing from `out` were not requested from the entry point run)
+    if "vdisp" in out:
+        assert np.array_equal(out["vdisp"][b], r.m_y)
     # S2 path points
     assert info[3] == r.n_my
     D1 = d_max + 1
@@ -114,7 +119,8 @@ def compare_frame(out, b, grey, disp, d_max, params=None, stream_id=0, frame_idx
     assert np.array_equal(fr["trace"][0, : r.beta.rounds], r.trace_beta)
     assert info[0] == r.flags, (info[0], r.flags)
     if r.beta.ok:
-        assert np.array_equal(out["beta"][b], np.array(r.beta.raw[:3]))
+        if "beta" in out:
+            assert np.array_equal(out["beta"][b], np.array(r.beta.raw[:3]))
         assert np.array_equal(fr["tables"][0], r.f) and np.array_equal(fr["tables"][1], r.fp)
         assert np.array_equal(fr["tables"][2], r.vpy)
     if r.flags & 1:
@@ -140,19 +146,21 @@ def compare_frame(out, b, grey, disp, d_max, params=None, stream_id=0, frame_idx
         return r
     rows = np.arange(r.v_h, H)
     assert np.array_equal(fr["tables"][3][rows], r.vpx[rows])
-    assert np.array_equal(out["vp"][b][rows, 0], r.vpx[rows]) and np.array_equal(out["vp"][b][rows, 1], r.vpy[rows])
+    if "vp" in out:
+        assert np.array_equal(out["vp"][b][rows, 0], r.vpx[rows]) and np.array_equal(out["vp"][b][rows, 1], r.vpy[rows])
     assert info[2] == r.v_end
     # S9-S12 energies
     E = fr["energy"]
     ok = _tol_ok(E, r.energy)
     assert ok.all(), f"energy mismatch at {np.nonzero(~ok)[0][:10]}: {E[~ok][:5]} vs {r.energy[~ok][:5]}"
-    assert _tol_ok(out["energy_f32"][b].astype(np.float64), r.energy).all()
+    if "energy_f32" in out:
+        assert _tol_ok(out["energy_f32"][b].astype(np.float64), r.energy).all()
     # S13 lanes and curves
     L = out["lanes"][b]
     assert L["flags"] == r.flags and L["v_h"] == r.v_h and L["v_end"] == r.v_end
     got_lanes = L["u_start"][: L["n"]]
     assert _lanes_match(got_lanes, r, r.energy, W), (got_lanes, r.u_start)
-    if list(got_lanes) == list(r.u_start):
+    if "curves" in out and list(got_lanes) == list(r.u_start):
         for l in range(L["n"]):
             rows = np.arange(r.v_end, H)
             assert np.abs(out["curves"][b, l, rows] - r.curves[l, rows]).max() < 1e-3
@@ -243,6 +251,31 @@ def test_seeded_gamma_and_literal_ransac():
     seed = np.array([[600.0, 0.1, 0.0, 0.0, 0.0]])
     out = run_gpu(g[None], d[None], 128, seed_gamma=seed)
     compare_frame(out, 0, g, d, 128, seed_gamma=seed[0])
+
+
+def test_bench_launch_sampled_frames():
+    # the benchmark's launch: 1024 frames of 1242x375 (f32 disparity, d_max 128) through
+    # ld_detect in one call; eight batch positions drawn with a fixed seed are checked against
+    # the oracle step by step.  64 synthetic frames (4 sequences x 16) are tiled to 1024; each
+    # position has its own frame index, so its RANSAC draws are its own.
+    ld = _ld()
+    parts = [synth.make_batch("c2", s, 16) for s in range(4)]
+    G = np.concatenate([p[0] for p in parts] * 16)
+    D = np.concatenate([p[1] for p in parts] * 16)
+    B, H, W = G.shape
+    assert (B, H, W) == (1024, 375, 1242) and D.dtype == np.float32
+    det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
+    lanes = det.lanes_buffer()
+    det.detect(torch.from_numpy(G).cuda(), torch.from_numpy(D).cuda(), lanes)
+    det.sync()
+    L = ld.Detector.parse_lanes(lanes)
+    rng = np.random.default_rng(1807)
+    picks = sorted(int(x) for x in rng.choice(B, 8, replace=False))
+    frames = {b: read_frame(det, b, H, W) for b in picks}
+    det.close()
+    for b in picks:
+        print("bench launch: frame", b, flush=True)
+        compare_frame({"lanes": L, "frames": frames}, b, G[b], D[b], 128)
 
 
 def test_batch_invariance_and_determinism():
