@@ -288,6 +288,44 @@ def test_pruned_path_matches_oracle_on_c2(cfg):
     assert 0 in kinds            # the narrowed search itself ran to the end
 
 
+def test_pruned_bench_launch_sampled_frames():
+    # the benchmark's learned-pruned launch: 1024 frames of 1242x375 (f32 disparity) through
+    # ld_detect_pruned in one call with one band; eight batch positions drawn with a fixed seed
+    # against the oracle's narrowed search fed with the GPU network's decisions.  64 synthetic
+    # frames (4 sequences x 16) are tiled to 1024, each position with its own frame index.
+    ld = _ld()
+    parts = [frames_c2(16, seed=s) for s in range(4)]
+    G = np.concatenate([p[0] for p in parts] * 16)
+    D = np.concatenate([p[1] for p in parts] * 16)
+    B, H, W = G.shape
+    assert (B, H, W) == (1024, 375, 1242)
+    net = ld.Cnn(bright_params(), n_bands=1)
+    det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
+    lanes = det.lanes_buffer()
+    det.detect_pruned(net, torch.from_numpy(G).cuda(), torch.from_numpy(D).cuda(), lanes)
+    det.sync()
+    L = ld.Detector.parse_lanes(lanes)
+    rng = np.random.default_rng(1807)
+    picks = sorted(int(x) for x in rng.choice(B, 8, replace=False))
+    frames = {}
+    for b in picks:
+        frames[b] = {
+            "info": det.read(ld.LD_STATE_INFO, b), "gamma": det.read(ld.LD_STATE_GAMMA, b)[0],
+            "mx": det.read(ld.LD_STATE_MX_PATH, b), "energy": det.read(ld.LD_STATE_ENERGY, b),
+            "bits": det.read(ld.LD_STATE_LANE_BITS, b), "prune": det.read(ld.LD_STATE_PRUNE, b),
+            "mask": det.read(ld.LD_STATE_CAND_MASK, b), "trace": det.read(ld.LD_STATE_TRACE, b).reshape(2, 64, 3),
+        }
+    cfgv = net.config
+    det.close()
+    net.close()
+    kinds = set()
+    for b in picks:
+        print("pruned bench launch: frame", b, flush=True)
+        r = _compare_pruned({"lanes": L, "frames": frames}, cfgv, b, G[b], D[b], 128, 1)
+        kinds.add(int(r.prune[1]))
+    assert 0 in kinds            # the narrowed search itself ran to the end on some of them
+
+
 def test_pruned_path_fallbacks_match_oracle():
     # a network that marks nothing: no seed, full search everywhere
     greys, disps = frames_c2(2, seed=5)
