@@ -730,6 +730,134 @@ static int band_top(int v_h, int H, int nb, int k) {
     return (H - 16) - ((R - 16) * k) / nb;
 }
 
+int ldref_band_top(int v_h, int H, int nb, int k) { return band_top(v_h, H, nb, k); }
+
+// Seed of the narrowed search: the vote columns of the road edges that the network marks on
+// the band rows, one histogram per band and one pooled.  est[k] is the first column of the
+// highest count of band k (-1 with no vote), cnt[k] its number of votes.  Returns the pooled
+// argmax c_s (smallest on ties), or -1 when fewer than min_votes votes were pooled.
+int ldref_seed(const int32_t* eu, const int32_t* ev, const int32_t* ebin, int ne, const uint8_t* lane_bits,
+               int W, int H, int v_h, int nb, int min_votes, int32_t* est, int32_t* cnt, int32_t* total) {
+    const int W2 = 2 * W;
+    std::vector<int> hp(W2, 0), hb(W2);
+    for (int k = 0; k < 4; ++k) { est[k] = -1; cnt[k] = 0; }
+    for (int k = 0; k < nb; ++k) {
+        const int top = band_top(v_h, H, nb, k);
+        if (top < 0) break;
+        std::fill(hb.begin(), hb.end(), 0);
+        for (int i = 0; i < ne; ++i) {
+            const int r = ev[i] - top;
+            if (r < 0 || r >= 16 || ebin[i] < 0 || !lane_bits[((size_t)k * 16 + r) * W + eu[i]]) continue;
+            hb[ebin[i]] += 1;
+            hp[ebin[i]] += 1;
+        }
+        int tot = 0, best = 0;
+        for (int c = 0; c < W2; ++c) { tot += hb[c]; if (hb[c] > hb[best]) best = c; }
+        est[k] = tot > 0 ? best : -1;
+        cnt[k] = tot;
+    }
+    int tot = 0, cs = 0;
+    for (int c = 0; c < W2; ++c) { tot += hp[c]; if (hp[c] > hp[cs]) cs = c; }
+    *total = tot;
+    return tot < min_votes ? -1 : cs;
+}
+
+// The row DP of ldref_row_dp restricted to the columns lo..hi: the same recursion, tie order
+// and backtrace, with every transition that leaves the window removed.  cpath[v] gets the
+// column (0..W2-1) on the road rows.  Returns 1 when the path reaches an inner edge of the
+// window (column lo with lo > 0, or column hi with hi < W2 - 1), else 0.
+int ldref_window_dp(const int64_t* mx, int H, int W2, int v_h, int tau_max, int lambda, int lo, int hi,
+                    int32_t* cpath) {
+    const int v_max = H - 1, R = v_max - v_h + 1, win = hi - lo + 1;
+    std::vector<int64_t> E(win), En(win);
+    std::vector<int8_t> back((size_t)R * win, 0);
+    for (int c = 0; c < win; ++c) E[c] = mx[(size_t)v_max * W2 + lo + c];
+    for (int v = v_max - 1; v >= v_h; --v) {
+        for (int c = 0; c < win; ++c) {
+            int64_t best = E[c];
+            int bt = 0;
+            for (int a = 1; a <= tau_max; ++a)
+                for (int sgn = -1; sgn <= 1; sgn += 2) {
+                    const int cc = c + sgn * a;
+                    if (cc < 0 || cc >= win) continue;
+                    const int64_t val = E[cc] + (int64_t)lambda * a;
+                    if (val < best) { best = val; bt = sgn * a; }
+                }
+            En[c] = mx[(size_t)v * W2 + lo + c] + best;
+            back[(size_t)(v - v_h) * win + c] = (int8_t)bt;
+        }
+        std::swap(E, En);
+    }
+    int c = 0;
+    for (int cc = 1; cc < win; ++cc)
+        if (E[cc] < E[c]) c = cc;
+    int touch = 0;
+    for (int v = v_h; v <= v_max; ++v) {
+        if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
+        cpath[v] = lo + c;
+        if (v < v_max) c += back[(size_t)(v - v_h) * win + c];
+    }
+    return touch;
+}
+
+// The track of Eq. lane_visualisation as one affine map of the start column per row:
+// u_v = fma(a_v, u_start, b_v), with a_{v_max} = 1, b_{v_max} = 0 and, going up one row,
+// a_v = B_v a_{v+1}, b_v = fma(B_v, b_{v+1}, A_v) (A_v, B_v as in the energy step).  Written for
+// the rows max(v_lo, v_end) .. v_max.
+int ldref_track_affine(const double* vpx, const double* vpy, int H, int v_end, int v_lo, double* a_out,
+                       double* b_out) {
+    const int v_max = H - 1;
+    double a = 1.0, c = 0.0;
+    for (int v = v_max; v >= std::max(v_lo, v_end); --v) {
+        if (v < v_max) {
+            const double den = (double)(v + 1) - vpy[v + 1];
+            const double Av = vpx[v + 1] / den;
+            const double Bv = ((double)v - vpy[v + 1]) / den;
+            a = Bv * a;
+            c = std::fma(Bv, c, Av);
+        }
+        a_out[v] = a;
+        b_out[v] = c;
+    }
+    return 0;
+}
+
+// Candidate mask of the narrowed search: candidate i (u_start = i - W/2) is hit when its track
+// column floor(u_v + 0.5) on a band row v >= v_end is a marked pixel; keep = hit dilated by
+// `dilate` candidates.  Returns the number kept.
+int ldref_cand_mask(const uint8_t* lane_bits, int W, int H, int v_h, int v_end, int nb, int dilate,
+                    const double* vpx, const double* vpy, uint8_t* hit_out, uint8_t* keep_out) {
+    const int W2 = 2 * W, half = W / 2, v_max = H - 1;
+    std::vector<double> av(H, 0.0), bv(H, 0.0);
+    const int top_hi = band_top(v_h, H, nb, nb - 1);
+    ldref_track_affine(vpx, vpy, H, v_end, top_hi, av.data(), bv.data());
+    std::vector<uint8_t> hit(W2, 0);
+    for (int i = 0; i < W2; ++i) {
+        const double us = (double)(i - half);
+        for (int k = 0; k < nb && !hit[i]; ++k) {
+            const int top = band_top(v_h, H, nb, k);
+            for (int r = 0; r < 16; ++r) {
+                const int v = top + r;
+                if (v < v_end || v > v_max) continue;
+                const double x = std::fma(av[v], us, bv[v]) + 0.5;
+                if (x >= 0.0 && x < (double)W) {
+                    const int col = (int)std::floor(x);
+                    if (lane_bits[((size_t)k * 16 + r) * W + col]) { hit[i] = 1; break; }
+                }
+            }
+        }
+    }
+    int kept = 0;
+    for (int i = 0; i < W2; ++i) {
+        uint8_t k = 0;
+        for (int j = std::max(0, i - dilate); j <= std::min(W2 - 1, i + dilate); ++j) k |= hit[j];
+        keep_out[i] = k;
+        kept += k;
+        if (hit_out) hit_out[i] = hit[i];
+    }
+    return kept;
+}
+
 static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
                        int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
                        const double* seed_gamma, ldref_out* o, ldref_learned* L);
@@ -824,29 +952,12 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
     if (L) {
         // seed from the votes of marking edges on the bands
         const int nb = L->n_bands;
-        std::vector<int> hp(W2, 0), hb(W2);
-        int est[4] = {-1, -1, -1, -1}, cnt[4] = {0, 0, 0, 0};
-        for (int k = 0; k < nb; ++k) {
-            const int top = band_top(v_h, H, nb, k);
-            if (top < 0) break;
-            std::fill(hb.begin(), hb.end(), 0);
-            for (int i = 0; i < ne; ++i) {
-                const int r = ev[i] - top;
-                if (r < 0 || r >= 16 || ebin[i] < 0 || !L->lane_bits[((size_t)k * 16 + r) * W + eu[i]]) continue;
-                hb[ebin[i]] += 1;
-                hp[ebin[i]] += 1;
-            }
-            int tot = 0, best = 0;
-            for (int c = 0; c < W2; ++c) { tot += hb[c]; if (hb[c] > hb[best]) best = c; }
-            est[k] = tot > 0 ? best : -1;
-            cnt[k] = tot;
-        }
-        int tot = 0, cs = 0;
-        for (int c = 0; c < W2; ++c) { tot += hp[c]; if (hp[c] > hp[cs]) cs = c; }
+        int32_t est[4], cnt[4], tot = 0;
+        int cs = ldref_seed(eu.data(), ev.data(), ebin.data(), ne, L->lane_bits, W, H, v_h, nb, L->min_votes, est,
+                            cnt, &tot);
         int lo = 0, hi = -1;
-        if (tot < L->min_votes) {
+        if (cs < 0) {
             fb = 1 | 4;
-            cs = -1;
         } else {
             lo = std::max(0, cs - L->delta_x);
             hi = std::min(W2 - 1, cs + L->delta_x);
@@ -870,34 +981,8 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
         for (int k = 0; k < 4; ++k) { L->prune[6 + k] = est[k]; L->prune[10 + k] = cnt[k]; }
         if (!(fb & 1)) {
             // the row DP of O10 restricted to columns lo..hi
-            const int win = hi - lo + 1, tau_max = P->tau_x_max;
-            std::vector<int64_t> E(win), En(win);
-            std::vector<int8_t> back((size_t)R * win, 0);
-            for (int c = 0; c < win; ++c) E[c] = mx[(size_t)v_max * W2 + lo + c];
-            for (int v = v_max - 1; v >= v_h; --v) {
-                for (int c = 0; c < win; ++c) {
-                    int64_t best = E[c];
-                    int bt = 0;
-                    for (int a = 1; a <= tau_max; ++a)
-                        for (int sgn = -1; sgn <= 1; sgn += 2) {
-                            const int cc = c + sgn * a;
-                            if (cc < 0 || cc >= win) continue;
-                            const int64_t val = E[cc] + (int64_t)P->lambda_x * a;
-                            if (val < best) { best = val; bt = sgn * a; }
-                        }
-                    En[c] = mx[(size_t)v * W2 + lo + c] + best;
-                    back[(size_t)(v - v_h) * win + c] = (int8_t)bt;
-                }
-                std::swap(E, En);
-            }
-            int c = 0;
-            for (int cc = 1; cc < win; ++cc)
-                if (E[cc] < E[c]) c = cc;
-            for (int v = v_h; v <= v_max; ++v) {
-                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) fb |= 1 | 8;
-                cpath[v] = lo + c;
-                if (v < v_max) c += back[(size_t)(v - v_h) * win + c];
-            }
+            if (ldref_window_dp(mx.data(), H, W2, v_h, P->tau_x_max, P->lambda_x, lo, hi, cpath.data()))
+                fb |= 1 | 8;
         }
         L->prune[1] = fb;
     }
@@ -944,44 +1029,9 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
     const int dn = P->d_nms > 0 ? P->d_nms : std::max(8, W / 64);
     if (L && !(fb & 1) && L->dilate >= 0) {
         // candidate mask: tracks through the band rows, u_v = fma(a_v, u_start, b_v)
-        const int nb = L->n_bands;
-        std::vector<double> Av(H, 0.0), Bv(H, 0.0);
-        for (int v = v_max - 1; v >= o->v_end; --v) {
-            const double den = (double)(v + 1) - vpy[v + 1];
-            Av[v] = vpx[v + 1] / den;
-            Bv[v] = ((double)v - vpy[v + 1]) / den;
-        }
-        const int top_hi = band_top(v_h, H, nb, nb - 1);
-        std::vector<double> ta((size_t)nb * 16, 0.0), tb((size_t)nb * 16, 0.0);
-        double a = 1.0, c = 0.0;
-        for (int v = v_max; v >= top_hi; --v) {
-            if (v < v_max) { a = Bv[v] * a; c = std::fma(Bv[v], c, Av[v]); }
-            for (int k = 0; k < nb; ++k) {
-                const int r = v - band_top(v_h, H, nb, k);
-                if (r >= 0 && r < 16) { ta[(size_t)k * 16 + r] = a; tb[(size_t)k * 16 + r] = c; }
-            }
-        }
-        std::vector<uint8_t> hit(W2, 0), keep(W2, 0);
-        for (int i = 0; i < W2; ++i) {
-            const double us = (double)(i - half);
-            for (int k = 0; k < nb && !hit[i]; ++k) {
-                const int top = band_top(v_h, H, nb, k);
-                for (int r = 0; r < 16; ++r) {
-                    if (top + r < o->v_end) continue;
-                    const double x = std::fma(ta[(size_t)k * 16 + r], us, tb[(size_t)k * 16 + r]) + 0.5;
-                    if (x >= 0.0 && x < (double)W) {
-                        const int col = (int)std::floor(x);
-                        if (L->lane_bits[((size_t)k * 16 + r) * W + col]) { hit[i] = 1; break; }
-                    }
-                }
-            }
-        }
-        int kept = 0;
-        for (int i = 0; i < W2; ++i) {
-            for (int j = std::max(0, i - L->dilate); j <= std::min(W2 - 1, i + L->dilate); ++j) keep[i] |= hit[j];
-            kept += keep[i];
-        }
-        L->prune[14] = kept;
+        std::vector<uint8_t> keep(W2, 0);
+        L->prune[14] = ldref_cand_mask(L->lane_bits, W, H, v_h, o->v_end, L->n_bands, L->dilate, vpx.data(),
+                                       vpy.data(), nullptr, keep.data());
         if (L->cand_mask) std::memcpy(L->cand_mask, keep.data(), W2);
         std::vector<double> Em(W2);
         for (int i = 0; i < W2; ++i) Em[i] = keep[i] ? E[i] : 0.0;

@@ -48,6 +48,7 @@ class FitOut(C.Structure):
 
 _P32 = C.POINTER(C.c_int32)
 _PD = C.POINTER(C.c_double)
+_P64 = C.POINTER(C.c_int64)
 
 
 class Out(C.Structure):
@@ -83,7 +84,6 @@ def lib():
                                    C.c_uint64, C.c_uint64, C.c_int64, C.c_int, _PD, C.POINTER(FitOut), _P32]
         L.ldref_road_tables.argtypes = [C.POINTER(FitOut), C.c_int, _PD, _PD, _PD, _P32]
         L.ldref_sobel.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P32, _P32]
-        _P64 = C.POINTER(C.c_int64)
         L.ldref_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, _P32]
         L.ldref_road_edges.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, _PD,
                                        C.c_int, C.c_double, C.c_int, _P32, _P32, _P32, _P32, C.c_int]
@@ -94,6 +94,13 @@ def lib():
         L.ldref_m0m1.argtypes = [_PD, C.c_int, C.c_int, C.c_int, C.c_int, _PD, _PD]
         L.ldref_energy.argtypes = [_PD, _PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD, _P32, C.c_int]
         L.ldref_peaks.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_int, _P32, _PD]
+        L.ldref_band_top.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.ldref_seed.argtypes = [_P32, _P32, _P32, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                 _P32, _P32, _P32]
+        L.ldref_window_dp.argtypes = [_P64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _P32]
+        L.ldref_track_affine.argtypes = [_PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD]
+        L.ldref_cand_mask.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _PD, _PD,
+                                      C.c_void_p, C.c_void_p]
         L.ldref_detect.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.POINTER(Params), C.c_uint64, C.c_int64, _PD, C.POINTER(Out)]
         L.ldref_detect_pruned.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int,
@@ -217,6 +224,56 @@ def row_dp(mx, v_h: int, tau_max: int = 5, lam: int = 1):
     cpath = np.full(H, -1, np.int32)
     lib().ldref_row_dp(mx.ctypes.data_as(C.POINTER(C.c_int64)), H, W2, v_h, tau_max, lam, _p32(cpath))
     return cpath
+
+
+def band_top(v_h: int, H: int, n_bands: int, k: int) -> int:
+    return int(lib().ldref_band_top(v_h, H, n_bands, k))
+
+
+def seed(eu, ev, ebin, lane_bits, W: int, H: int, v_h: int, n_bands=1, min_votes=8):
+    """Seed of the narrowed search: (c_s or -1, est[4], cnt[4], pooled votes)."""
+    eu, ev, ebin = [np.ascontiguousarray(a, dtype=np.int32) for a in (eu, ev, ebin)]
+    bits = np.ascontiguousarray(lane_bits, dtype=np.uint8).reshape(4, 16, W)
+    est = np.zeros(4, np.int32)
+    cnt = np.zeros(4, np.int32)
+    tot = np.zeros(1, np.int32)
+    cs = lib().ldref_seed(_p32(eu), _p32(ev), _p32(ebin), len(eu), bits.ctypes.data, W, H, v_h, n_bands, min_votes,
+                          _p32(est), _p32(cnt), _p32(tot))
+    return int(cs), est, cnt, int(tot[0])
+
+
+def window_dp(mx, v_h: int, lo: int, hi: int, tau_max: int = 5, lam: int = 1):
+    """Row DP restricted to columns lo..hi: (path columns, touched an inner window edge)."""
+    mx = np.ascontiguousarray(mx, dtype=np.int64)
+    H, W2 = mx.shape
+    cpath = np.full(H, -1, np.int32)
+    touch = lib().ldref_window_dp(mx.ctypes.data_as(C.POINTER(C.c_int64)), H, W2, v_h, tau_max, lam, lo, hi,
+                                  _p32(cpath))
+    return cpath, bool(touch)
+
+
+def track_affine(vpx, vpy, v_end: int, v_lo: int):
+    """Per-row (a_v, b_v) of the track u_v = fma(a_v, u_start, b_v); NaN outside the rows written."""
+    vpx = np.ascontiguousarray(vpx, dtype=np.float64)
+    vpy = np.ascontiguousarray(vpy, dtype=np.float64)
+    H = len(vpx)
+    a = np.full(H, np.nan)
+    b = np.full(H, np.nan)
+    lib().ldref_track_affine(_pd(vpx), _pd(vpy), H, v_end, v_lo, _pd(a), _pd(b))
+    return a, b
+
+
+def cand_mask(lane_bits, W: int, v_h: int, v_end: int, vpx, vpy, n_bands=1, dilate=0):
+    """(hit, keep, kept) of the narrowed search's candidate mask."""
+    bits = np.ascontiguousarray(lane_bits, dtype=np.uint8).reshape(4, 16, W)
+    vpx = np.ascontiguousarray(vpx, dtype=np.float64)
+    vpy = np.ascontiguousarray(vpy, dtype=np.float64)
+    H = len(vpx)
+    hit = np.zeros(2 * W, np.uint8)
+    keep = np.zeros(2 * W, np.uint8)
+    kept = lib().ldref_cand_mask(bits.ctypes.data, W, H, v_h, v_end, n_bands, dilate, _pd(vpx), _pd(vpy),
+                                 hit.ctypes.data, keep.ctypes.data)
+    return hit, keep, int(kept)
 
 
 def weights(eu, ev, egx, egy, vpx, vpy, sigma_g=3.5, squared=0):
