@@ -167,6 +167,30 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
                     const uint64_t* stream_ids, const int64_t* frame_idx, ld_lanes* lanes_out, float* curves_out,
                     void* hip_stream);
 
+/* Scratch of ld_detect_noalloc, per GPU (64 MiB). */
+#define LD_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* ld_detect for callers that cannot allocate device memory (work recorded under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc): the same kernels and results as
+ * ld_frame_create + ld_detect + ld_frame_destroy with these sizes and parameters, but the
+ * scratch is a fixed device array of LD_NOALLOC_SCRATCH_BYTES built into the library (each
+ * GPU the library runs on holds its own copy from the first call there until the process
+ * ends).  No device or host memory is allocated and nothing is freed.
+ *  width, height, batch, fmt, d_max, p : as in ld_frame_create (LD_E_INVAL outside its
+ *                     limits).  The frame object's scratch for these sizes must fit the
+ *                     array, else LD_E_NOMEM and nothing is enqueued: about 6.1 MiB per
+ *                     1242 x 375 frame (d_max 128; batch <= 10), 27.2 MiB per 1920 x 1080
+ *                     frame (d_max 255; batch <= 2), 1.7 MiB per 640 x 192 frame.
+ *  grey ... hip_stream : as in ld_detect.
+ * The array keeps the last call's contents; every call on one GPU shares it, so calls that
+ * may overlap on a GPU (other streams, other host threads) must be ordered by the caller:
+ * overlapping calls race and their results are undefined.  The first call on a device
+ * looks up that device's copy (a lock is taken then; later calls only read it). */
+ld_status ld_detect_noalloc(int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
+                            const ld_params* p, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                            int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
+                            ld_lanes* lanes_out, float* curves_out, void* hip_stream);
+
 /* Wait for the frame object's last stream; a failure of enqueued work surfaces here as
  * LD_E_HIP. */
 ld_status ld_sync(ld_frame f);

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 #include <type_traits>
 
@@ -2210,6 +2211,49 @@ ld_status check_params(const ld_params& p) {
     return LD_OK;
 }
 
+// Point the scratch fields of d at the regions of one allocation laid out by frame_layout.
+void bind_regions(Dev& d, char* base, const size_t* off) {
+    d.myT = reinterpret_cast<int32_t*>(base + off[0]);
+    d.back_y = reinterpret_cast<uint8_t*>(base + off[1]);
+    d.my_pts = reinterpret_cast<int32_t*>(base + off[2]);
+    d.fit = reinterpret_cast<FitRes*>(base + off[3]);
+    d.info = reinterpret_cast<FrameInfo*>(base + off[4]);
+    d.tab = reinterpret_cast<double*>(base + off[5]);
+    d.rowcnt = reinterpret_cast<int32_t*>(base + off[6]);
+    d.edges = reinterpret_cast<ld_edge*>(base + off[7]);
+    d.back_x = reinterpret_cast<int8_t*>(base + off[8]);
+    d.mxpath = reinterpret_cast<int32_t*>(base + off[9]);
+    d.energy = reinterpret_cast<double*>(base + off[10]);
+    d.trace = reinterpret_cast<int32_t*>(base + off[11]);
+    d.qbuf = reinterpret_cast<float*>(base + off[12]);
+    d.rbound = reinterpret_cast<uint32_t*>(base + off[13]);
+    d.lbits = reinterpret_cast<uint8_t*>(base + off[14]);
+    d.prune = reinterpret_cast<int32_t*>(base + off[15]);
+    d.cmask = reinterpret_cast<uint8_t*>(base + off[16]);
+    d.seedg = reinterpret_cast<double*>(base + off[17]);
+    d.nact = nullptr;
+    d.only = nullptr;
+    d.only_bits = 0;
+    d.only_set = 0;
+}
+
+// Sizes, parameters and derived launch constants of a frame object (no device memory).
+ld_status init_dev(Dev& d, int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
+                   const ld_params* p) {
+    if (width < 8 || width > 4096 || height < 8 || height > 4096 || batch < 1 || batch > 65535) return LD_E_INVAL;
+    if (fmt < 0 || fmt > 2 || d_max < 1 || d_max > 1023) return LD_E_INVAL;
+    ld_params P;
+    ld_params_default(&P);
+    if (p) P = *p;
+    if (check_params(P) != LD_OK) return LD_E_INVAL;
+    // the row DP keeps (E << 4 | rank) in int32: E >= -width * height * (2 chi + 1)
+    if ((int64_t)width * height * (2 * (int64_t)P.chi + 1) + 5 * (int64_t)P.lambda_x >= ((int64_t)1 << 27)) return LD_E_INVAL;
+    d.W = width; d.H = height; d.D1 = d_max + 1; d.W2 = 2 * width; d.half = width / 2; d.fmt = fmt;
+    d.d_max = d_max; d.B = batch; d.P = P;
+    d.hist_rows = std::max(kHistGroup, std::min(32, (8192 / d.D1) / kHistGroup * kHistGroup));
+    return LD_OK;
+}
+
 template <int FMT>
 void launch_hist(int npt, dim3 g, size_t lds, hipStream_t st, const Dev& d, const uint8_t* dp, int64_t pitch,
                  int32_t* out) {
@@ -2342,6 +2386,53 @@ ld_status check_images(ld_frame f, const uint8_t* grey, int64_t gp, const void* 
     return LD_OK;
 }
 
+// Every step of ld_detect on the active frames of f, on one stream.
+ld_status detect_all(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt,
+                     const uint64_t* sid, const int64_t* fidx, ld_lanes* lanes, float* curves, hipStream_t st) {
+    f->last = st;
+    ld_status s = run_vdisp(f, disp, dpt, sid, fidx, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_vp(f, grey, gp, disp, dpt, sid, fidx, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st);
+    if (s == LD_OK) s = run_peaks(f, lanes, curves, st);
+    f->stage = s == LD_OK ? 3 : 0;
+    f->bands = 0;
+    return s;
+}
+
+}  // namespace
+
+// Scratch of ld_detect_noalloc: a fixed device array, one copy per GPU for the life of the
+// process.  Host code never uses the name `scratch` as an address: the device address of each
+// GPU's copy is taken once per device with hipGetSymbolAddress (that device current) and kept
+// in scratch_ptr.  Every ld_detect_noalloc call on a GPU uses that GPU's copy, so calls that
+// overlap on one GPU (different streams or threads without ordering) race on it.
+constexpr size_t kNoAllocBytes = LD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+char* scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (set up on the first call on that device).
+ld_status noalloc_scratch(char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LD_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return LD_E_INVAL;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return LD_E_HIP;
+        }
+        scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = scratch_ptr[dev];
+    return LD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2370,48 +2461,19 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
                           const ld_params* p, ld_frame* out) {
     if (!out) return LD_E_INVAL;
     *out = nullptr;
-    if (width < 8 || width > 4096 || height < 8 || height > 4096 || batch < 1 || batch > 65535) return LD_E_INVAL;
-    if (fmt < 0 || fmt > 2 || d_max < 1 || d_max > 1023) return LD_E_INVAL;
-    ld_params P;
-    ld_params_default(&P);
-    if (p) P = *p;
-    if (check_params(P) != LD_OK) return LD_E_INVAL;
-    // the row DP keeps (E << 4 | rank) in int32: E >= -width * height * (2 chi + 1)
-    if ((int64_t)width * height * (2 * (int64_t)P.chi + 1) + 5 * (int64_t)P.lambda_x >= ((int64_t)1 << 27)) return LD_E_INVAL;
+    Dev d0{};
+    if (init_dev(d0, width, height, batch, fmt, d_max, p) != LD_OK) return LD_E_INVAL;
     ld_frame f = new (std::nothrow) ld_frame_s();
     if (!f) return LD_E_NOMEM;
     Dev& d = f->d;
-    d.W = width; d.H = height; d.D1 = d_max + 1; d.W2 = 2 * width; d.half = width / 2; d.fmt = fmt;
-    d.d_max = d_max; d.B = batch; d.P = P;
-    d.hist_rows = std::max(kHistGroup, std::min(32, (8192 / d.D1) / kHistGroup * kHistGroup));
+    d = d0;
     size_t off[kRegions], sz[kRegions];
     const size_t o = frame_layout(width, height, batch, d_max, off, sz);
 
     if (hipGetDevice(&f->device) != hipSuccess) { delete f; return LD_E_HIP; }
     if (hipMalloc(&f->mem, o) != hipSuccess) { (void)hipGetLastError(); delete f; return LD_E_NOMEM; }
     f->mem_bytes = o;
-    char* base = static_cast<char*>(f->mem);
-    d.myT = reinterpret_cast<int32_t*>(base + off[0]);
-    d.back_y = reinterpret_cast<uint8_t*>(base + off[1]);
-    d.my_pts = reinterpret_cast<int32_t*>(base + off[2]);
-    d.fit = reinterpret_cast<FitRes*>(base + off[3]);
-    d.info = reinterpret_cast<FrameInfo*>(base + off[4]);
-    d.tab = reinterpret_cast<double*>(base + off[5]);
-    d.rowcnt = reinterpret_cast<int32_t*>(base + off[6]);
-    d.edges = reinterpret_cast<ld_edge*>(base + off[7]);
-    d.back_x = reinterpret_cast<int8_t*>(base + off[8]);
-    d.mxpath = reinterpret_cast<int32_t*>(base + off[9]);
-    d.energy = reinterpret_cast<double*>(base + off[10]);
-    d.trace = reinterpret_cast<int32_t*>(base + off[11]);
-    d.qbuf = reinterpret_cast<float*>(base + off[12]);
-    d.rbound = reinterpret_cast<uint32_t*>(base + off[13]);
-    d.lbits = reinterpret_cast<uint8_t*>(base + off[14]);
-    d.prune = reinterpret_cast<int32_t*>(base + off[15]);
-    d.cmask = reinterpret_cast<uint8_t*>(base + off[16]);
-    d.seedg = reinterpret_cast<double*>(base + off[17]);
-    d.only = nullptr;
-    d.only_bits = 0;
-    d.only_set = 0;
+    bind_regions(d, static_cast<char*>(f->mem), off);
     // small state starts zeroed so that introspection of an unprocessed frame is defined
     if (hipMemset(d.info, 0, sz[4]) != hipSuccess || hipMemset(d.trace, 0xff, sz[11]) != hipSuccess ||
         hipMemset(d.fit, 0, sz[3]) != hipSuccess || hipMemset(d.prune, 0, sz[15]) != hipSuccess ||
@@ -2421,7 +2483,6 @@ ld_status ld_frame_create(int32_t width, int32_t height, int32_t batch, int32_t 
         delete f;
         return LD_E_HIP;
     }
-    d.nact = nullptr;
     f->batch = batch;
     f->active = batch;
     f->last = nullptr;
@@ -2505,15 +2566,33 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
     if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
     if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
     if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    f->last = st;
-    ld_status s = run_vdisp(f, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
-    if (s == LD_OK) s = run_vp(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, nullptr, nullptr, st);
-    if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st);
-    if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st);
-    f->stage = s == LD_OK ? 3 : 0;
-    f->bands = 0;
-    return s;
+    return detect_all(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out,
+                      static_cast<hipStream_t>(hip_stream));
+}
+
+ld_status ld_detect_noalloc(int32_t width, int32_t height, int32_t batch, int32_t fmt, int32_t d_max,
+                            const ld_params* p, const uint8_t* grey, int64_t grey_pitch, const void* disp,
+                            int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
+                            ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    ld_frame_s fr;                      // host state on the stack; prof stays off (no event pool)
+    if (init_dev(fr.d, width, height, batch, fmt, d_max, p) != LD_OK) return LD_E_INVAL;
+    if (!lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
+    if (!grey || check_images(&fr, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
+    if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
+    if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
+    size_t off[kRegions], sz[kRegions];
+    if (frame_layout(width, height, batch, d_max, off, sz) > kNoAllocBytes) return LD_E_NOMEM;
+    char* base = nullptr;
+    const ld_status s = noalloc_scratch(&base);
+    if (s != LD_OK) return s;
+    bind_regions(fr.d, base, off);
+    fr.batch = batch;
+    fr.active = batch;
+    fr.mem = nullptr;
+    fr.mem_bytes = 0;
+    (void)hipGetDevice(&fr.device);
+    return detect_all(&fr, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out,
+                      static_cast<hipStream_t>(hip_stream));
 }
 
 ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,

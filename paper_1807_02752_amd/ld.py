@@ -127,6 +127,9 @@ def lib():
         L.ld_cnn_labels.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp, vp]
         L.ld_cnn_train_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp]
         L.ld_detect_pruned.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.ld_detect_noalloc.argtypes = [i32, i32, i32, i32, i32, C.POINTER(ld_params), vp, i64, vp, i64, vp, vp,
+                                        vp, vp, vp]
+        L.ld_detect_noalloc.restype = i32
         for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
                      "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"):
             getattr(L, name).restype = i32
@@ -143,7 +146,7 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times", "ld_server_create", "ld_server_destroy",
             "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
-            "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"]
+            "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -202,6 +205,16 @@ def ld_peaks(f, lanes_out, curves_out, stream):
 def ld_detect(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out, stream):
     return lib().ld_detect(f, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out,
                            stream)
+
+
+def ld_detect_noalloc(width, height, batch, fmt, d_max, params, grey, grey_pitch, disp, disp_pitch, stream_ids,
+                      frame_idx, lanes_out, curves_out, stream):
+    return lib().ld_detect_noalloc(width, height, batch, fmt, d_max,
+                                   C.byref(params) if params is not None else None, grey, grey_pitch, disp,
+                                   disp_pitch, stream_ids, frame_idx, lanes_out, curves_out, stream)
+
+
+LD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def ld_sync(f):

@@ -79,3 +79,19 @@ def test_server_config_validation_without_device(L):
         assert st == ld.LD_E_INVAL and not h.value
     assert ld.ld_server_destroy(None) == ld.LD_OK
     assert ld.ld_server_submit(None, 0, 0, None, 0, None, 0)[0] == ld.LD_E_INVAL
+
+
+def test_noalloc_argument_checks_without_device(L):
+    """ld_detect_noalloc validates sizes and rejects a scratch need beyond its fixed array
+    before any HIP call (the pointers below are never dereferenced)."""
+    from paper_1807_02752_amd import ld
+    fake = C.c_void_p(1 << 20)
+    args = lambda w, h, b, fmt, dm: (w, h, b, fmt, dm, None, fake, w, fake, w * 4, None, None, fake, None, None)
+    assert ld.ld_detect_noalloc(*args(4, 375, 1, ld.LD_DISP_F32, 128)) == ld.LD_E_INVAL
+    assert ld.ld_detect_noalloc(*args(1242, 375, 0, ld.LD_DISP_F32, 128)) == ld.LD_E_INVAL
+    assert ld.ld_detect_noalloc(*args(1242, 375, 1, 5, 128)) == ld.LD_E_INVAL
+    assert ld.ld_detect_noalloc(*args(1242, 375, 11, ld.LD_DISP_F32, 128)) == ld.LD_E_NOMEM
+    assert ld.ld_detect_noalloc(*args(1920, 1080, 3, ld.LD_DISP_F32, 255)) == ld.LD_E_NOMEM
+    no_lanes = list(args(1242, 375, 1, ld.LD_DISP_F32, 128))
+    no_lanes[12] = None
+    assert ld.ld_detect_noalloc(*no_lanes) == ld.LD_E_INVAL
