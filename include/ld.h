@@ -134,7 +134,7 @@ ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint6
  * (Eq. sparse_vpx_estimation), band accumulation (Alg. "Dense V_px accumulation"), DP path
  * (Eq. dense_vpx_estimation) and V_px by RANSAC (Alg. "gamma estimation",
  * Eq. vpx_estimation).  Needs a prior ld_vdisp on this frame object (else LD_E_STATE).
- *  grey, grey_pitch : uint8 grey frames, pitch >= width.
+ *  grey, grey_pitch : uint8 grey frames, pitch >= width, height * pitch < 2^31 - 4096.
  *  disp, disp_pitch : the same disparity frames as given to ld_vdisp.
  *  stream_ids, frame_idx : as in ld_vdisp (they key the V_px RANSAC samples).
  *  seed_gamma       : nullable device double n x 5, a raw-basis quartic in v used as

@@ -717,19 +717,32 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 }
 
 // ------------------------------------------------------------------------------------------
-// S4 + S5: Sobel gradient on the road rows, road mask (Sec. 2.3.1), edge test, and the V_px
+// S4 + S5: Sobel gradient on the road rows, edge test, road mask (Sec. 2.3.1) and the V_px
 // vote of every road edge (Eq. sparse_vpx_estimation with the gradient read as the edge
-// slope).  One wave covers 256 columns x kEdgeRows rows of one frame, four consecutive
-// columns per lane: each lane slides a 3-row window of six grey bytes (columns ub-1 .. ub+4)
-// down its columns with the grey row two steps ahead and the raw disparities of the next row
-// in flight.  The road test is an integer compare against the row's raw interval.  A row's
-// edges are appended to its bucket with one atomic per wave, written one step later.
-// Pixels outside the frame are never read for a result: the gradient is taken only at
-// 1 <= u <= W-2 and 1 <= v <= H-2, so the loads clamp their row and column into the frame
-// instead of masking (lanes whose six columns are all inside take the branch-free path).
-constexpr int kEdgeRows = 16;
+// slope).
+//
+// A workgroup takes kEdgeStrip rows of one frame across its whole width: wave w owns the 256
+// columns from 256 w, four consecutive columns per lane, and walks the rows down.  A row is
+// loaded as one aligned dword per lane (plus the dwords left and right of the wave's span for
+// its first and last lane); the six bytes a lane needs (columns ub-1 .. ub+4) come from its own
+// dword and its neighbours' by DPP lane shifts.  The loads go through a buffer resource bounded
+// by the frame's rows, so a dword outside the frame reads as 0 and is never fetched (those
+// bytes feed no result: the gradient is only taken at 1 <= u <= W-2, 1 <= v <= H-2).  Rows go
+// in groups of three, the loads of the next group issued before the current one is worked on.
+// Only the grey image is streamed: the edge test needs no disparity.  The edge pixels of a
+// wave are queued in LDS and, in batches of 64, each lane gathers the raw disparity of one
+// queued pixel, applies the road test (an integer compare against the row's raw interval),
+// takes the vote column and appends the record to its row's bucket (LDS slot counters of the
+// strip, so every bucket of the strip, and its count, is written by this workgroup alone and
+// nothing carries over from an earlier call).
+template <int N> using IntC = std::integral_constant<int, N>;
+
+constexpr int kEdgeStrip = 32;                        // rows per workgroup
+constexpr int kEdgeCols = 4 * kWave;                  // columns per wave
+constexpr int kEdgeQueue = 512;                       // queued edge pixels per wave
+constexpr int kEdgeFlushAt = kEdgeQueue - kEdgeCols;  // a row queues at most kEdgeCols
 static_assert(sizeof(ld_edge) == 8, "an edge record is written as one 8-byte store");
-constexpr int kQT = 64;                 // threads per workgroup (one wave), 4 columns each
+
 template <int FMT>
 __device__ __forceinline__ uint32_t disp_raw(const uint8_t* row, int u) {
     if (FMT == LD_DISP_U8) return row[u];
@@ -759,139 +772,170 @@ __device__ __forceinline__ int vote_bin(double tt, int gy, int gx, int u, int ha
     return (bf >= -(double)half && bf < (double)(W2 - half)) ? (int)bf + half : -1;
 }
 
+__device__ __forceinline__ uint32_t dpp_from_prev(uint32_t x) {   // lane l gets lane l-1's x
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t dpp_from_next(uint32_t x) {   // lane l gets lane l+1's x
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);
+}
+
 template <int FMT>
-__global__ __launch_bounds__(kQT) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
-                                               int64_t dpitch, const uint32_t* __restrict__ rbound,
-                                               const double* __restrict__ tab) {
-    const int b = blockIdx.z, vb = blockIdx.y * kEdgeRows, lane = threadIdx.x;
+__global__ __launch_bounds__(1024) void k_edges(Dev d, const uint8_t* grey, int64_t gpitch, const uint8_t* disp,
+                                                int64_t dpitch) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char esm[];   // strip tables, then the wave queues
+    const int b = blockIdx.y, s0 = blockIdx.x * kEdgeStrip;
     if (frame_masked(d, b)) return;
-    const int ub = (blockIdx.x * kQT + lane) * 4;
-    const int W = d.W, H = d.H;
+    const int W = d.W, H = d.H, t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    const int rows = min(kEdgeStrip, H - s0);
+    double* svpy = reinterpret_cast<double*>(esm);                      // V_py of the strip's rows
+    uint32_t* sbnd = reinterpret_cast<uint32_t*>(svpy + kEdgeStrip);    // raw road interval per row
+    int* scnt = reinterpret_cast<int*>(sbnd + 2 * kEdgeStrip);          // edges per row
+    uint2* queue = reinterpret_cast<uint2*>(scnt + kEdgeStrip) + wave * kEdgeQueue;
     const FrameInfo fi = d.info[b];
-    if (fi.flags & LD_FLAG_NOROAD) return;
-    const int vs = max(vb, fi.v_h), ve = min(vb + kEdgeRows - 1, H - 1);
-    if (vs > ve) return;
-    const double* tvpy = tab + (int64_t)b * 6 * H + 2 * H;      // read only here (scalar loads)
-    const uint32_t* rb = rbound + (int64_t)b * H * 2;
-    const int t2 = d.P.edge_t * d.P.edge_t;
-    const bool inner = ub >= 1 && ub + 4 <= W - 1;
-    const uint8_t* gbase = grey + (int64_t)b * H * gpitch;
-    const uint8_t* dbase = disp + (int64_t)b * H * dpitch;
-    // a grey row's six bytes (columns ub-1 .. ub+4) stay packed, four in lo and two in hi,
-    // until the step that uses them, so a row loaded ahead is not waited for early
-    struct Row6 { uint32_t lo, hi; };
-    auto load_row = [&](int v) -> Row6 {
-        const uint8_t* g = gbase + (int64_t)min(max(v, 0), H - 1) * gpitch;
-        Row6 r;
-        if (inner) {
-            __builtin_memcpy(&r.lo, g + ub - 1, 4);
-            uint16_t h;
-            __builtin_memcpy(&h, g + ub + 3, 2);
-            r.hi = h;
-        } else {
-            r.lo = 0u; r.hi = 0u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) r.lo |= (uint32_t)g[min(max(ub - 1 + k, 0), W - 1)] << (8 * k);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) r.hi |= (uint32_t)g[min(max(ub + 3 + k, 0), W - 1)] << (8 * k);
+    const bool road = !(fi.flags & LD_FLAG_NOROAD);
+    if (t < kEdgeStrip) {
+        scnt[t] = 0;
+        if (road && t < rows) {
+            const int64_t v = (int64_t)b * H + s0 + t;
+            svpy[t] = d.tab[(int64_t)b * 6 * H + 2 * H + s0 + t];
+            sbnd[2 * t] = d.rbound[2 * v];
+            sbnd[2 * t + 1] = d.rbound[2 * v + 1];
         }
-        return r;
-    };
-    auto unpack = [](const Row6& r, int* x) {
+    }
+    __syncthreads();
+    const int vs = max(max(s0, road ? fi.v_h : H), 1), ve = min(s0 + rows - 1, H - 2);
+    const int ub = wave * kEdgeCols + 4 * lane;
+    if (vs <= ve) {
+        // the frame's rows through a buffer resource: base aligned down to a dword, records up
+        // to the end of the frame's last row rounded up to a dword
+        const uintptr_t fbase = (uintptr_t)(grey + (int64_t)b * H * gpitch);
+        const uintptr_t abase = fbase & ~(uintptr_t)3;
+        const int nrec = (int)((((fbase + (uintptr_t)((int64_t)H * gpitch)) + 3) & ~(uintptr_t)3) - abase);
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(abase), 0, nrec, 0x00020000);
+        // every lane issues both loads; the extra one is fetched only by the first and last
+        // lane (the others give an offset past the records, which reads 0 without a fetch)
+        const int xoff = lane == 0 ? -4 : (lane == kWave - 1 ? 4 : INT32_MIN);
+        struct RowD { uint32_t own, ext; };
+        auto load_row = [&](int v) -> RowD {
+            const uintptr_t ra = fbase + (uintptr_t)((int64_t)min(max(v, 0), H - 1) * gpitch);
+            const int off = (int)((ra & ~(uintptr_t)3) - abase) + ub;
+            RowD r;
+            r.own = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+            r.ext = __builtin_amdgcn_raw_buffer_load_b32(rs, xoff == INT32_MIN ? INT32_MIN : off + xoff, 0, 0);
+            return r;
+        };
+        // columns ub-1 .. ub+4 of row v
+        auto unpack = [&](const RowD& r, int v, int* x) {
+            const uint32_t sh = (uint32_t)((fbase + (uintptr_t)((int64_t)min(max(v, 0), H - 1) * gpitch)) & 3);
+            uint32_t dp = dpp_from_prev(r.own), dn = dpp_from_next(r.own);
+            if (lane == 0) dp = r.ext;
+            if (lane == kWave - 1) dn = r.ext;
+            const uint32_t mid = __builtin_amdgcn_alignbyte(dn, r.own, sh);   // ub .. ub+3
+            const uint32_t lft = __builtin_amdgcn_alignbyte(r.own, dp, 3u);   // ub-sh-1 .. ub-sh+2
+            x[0] = (int)((lft >> (8u * sh)) & 255u);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = (int)((r.lo >> (8 * k)) & 255u);
-        x[4] = (int)(r.hi & 255u);
-        x[5] = (int)((r.hi >> 8) & 255u);
-    };
-    // rows v-1, v, v+1 of the current step and v+2 in flight
-    Row6 ga = load_row(vs - 1), gm = load_row(vs), gc = load_row(vs + 1);
-    uint32_t rc[4], rn[4];
-    auto load_raw = [&](int v, uint32_t* r) {
-        const uint8_t* dr = dbase + (int64_t)min(v, ve) * dpitch;
-        if (inner) {
+            for (int k = 0; k < 4; ++k) x[k + 1] = (int)((mid >> (8 * k)) & 255u);
+            x[5] = (int)((dn >> (8u * sh)) & 255u);
+        };
+        const int t2 = d.P.edge_t * d.P.edge_t;
+        bool colok[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[k] = disp_raw<FMT>(dr, ub + k);
-        } else {
+        for (int k = 0; k < 4; ++k) colok[k] = ub + k >= 1 && ub + k <= W - 2;
+        int qn = 0;
+        const uint8_t* dframe = disp + (int64_t)b * H * dpitch;
+        ld_edge* eframe = d.edges + (int64_t)b * H * W;
+        auto flush = [&]() {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (int i0 = 0; i0 < qn; i0 += kWave) {
+                const int i = i0 + lane;
+                if (i < qn) {
+                    const uint2 e = queue[i];
+                    const int u = (int)(e.x & 0xffffu), r = (int)(e.y >> 16);
+                    const int gx = (int)(int16_t)(e.x >> 16), gy = (int)(int16_t)(e.y & 0xffffu);
+                    const int v = s0 + r;
+                    const uint32_t raw = disp_raw<FMT>(dframe + (int64_t)v * dpitch, u);
+                    if (raw >= sbnd[2 * r] && raw <= sbnd[2 * r + 1]) {
+                        const int bin = gx != 0 ? vote_bin((double)v - svpy[r], gy, gx, u, d.half, d.W2) : -1;
+                        const int slot = atomicAdd(&scnt[r], 1);
+                        reinterpret_cast<uint2*>(eframe + (int64_t)v * W)[slot] =
+                            make_uint2(e.x, (uint32_t)(uint16_t)gy | ((uint32_t)(uint16_t)bin << 16));
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            qn = 0;
+        };
+        // Ring of three unpacked rows (rotated by renaming: at the step of phase P, rows v-1 and
+        // v sit in U[(P+2)%3] and U[P], and row v+1 is unpacked into U[(P+1)%3]) and two sets of
+        // three rows of loads: a group of steps consumes one set, whose loads were issued a
+        // whole group earlier, after issuing the other set's loads for the next group.  Steps
+        // past the strip's last row compute masked rows.
+        int U[3][6];
+        RowD LA[3], LB[3];
+        LA[0] = load_row(vs - 1);
+        LA[1] = load_row(vs);
+        unpack(LA[0], vs - 1, U[2]);
+        unpack(LA[1], vs, U[0]);
+        LA[0] = load_row(vs + 1);
+        LA[1] = load_row(vs + 2);
+        LA[2] = load_row(vs + 3);
+        int v = vs;
+        auto step = [&](auto Pc, const RowD& row_next) {
+            constexpr int P = decltype(Pc)::value;
+            constexpr int A = (P + 2) % 3, M = P % 3, C = (P + 1) % 3;
+            const bool rowok = v <= ve;
+            unpack(row_next, v + 1, U[C]);
+            int S[6], T[6];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[k] = disp_raw<FMT>(dr, min(ub + k, W - 1));
-        }
-    };
-    load_raw(vs, rc);
-    uint32_t lo = rb[2 * vs], hi = rb[2 * vs + 1];      // road interval and V_py of the current row
-    double vpy = tvpy[vs];
-    // A row's edges are written one step later: its slot atomic is issued at the end of its
-    // step and its records are stored at the end of the next step, after that step's work, so
-    // no wait for a store or an atomic result comes between a step's loads and its use of the
-    // previous step's loads (memory operations complete in order).
-    int p_v = -1, p_tot = 0, p_base = 0;
-    uint32_t p_rec[4] = {0u, 0u, 0u, 0u}, p_mask = 0;
-    int p_bin[4] = {-1, -1, -1, -1};
-    uint64_t p_bal[4] = {0, 0, 0, 0};
-    __builtin_amdgcn_s_waitcnt(0x0070);   // the prologue's loads (vector and scalar), so no path enters the loop with loads pending
-    auto flush = [&]() {
-        if (p_tot > 0) {
-            int off = __builtin_amdgcn_readlane(p_base, 0);
-            ld_edge* out = d.edges + ((int64_t)b * H + p_v) * W;
+            for (int j = 0; j < 6; ++j) {
+                S[j] = U[A][j] + 2 * U[M][j] + U[C][j];
+                T[j] = U[C][j] - U[A][j];
+            }
+            uint64_t bal[4];
+            int gxk[4], gyk[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                if (p_mask & (1u << k)) {   // one 8-byte store: (u, gx) and (gy, vote column)
-                    const uint2 e = make_uint2((uint32_t)(uint16_t)(ub + k) | (p_rec[k] << 16),
-                                               (p_rec[k] >> 16) | ((uint32_t)(uint16_t)p_bin[k] << 16));
-                    reinterpret_cast<uint2*>(out)[off + __popcll(p_bal[k] & lanes_below())] = e;
+                gxk[k] = S[k + 2] - S[k];
+                gyk[k] = T[k] + 2 * T[k + 1] + T[k + 2];
+                const int m2 = __mul24(gxk[k], gxk[k]) + __mul24(gyk[k], gyk[k]);
+                bal[k] = __ballot(colok[k] & rowok & (m2 > t2));
+            }
+            if ((bal[0] | bal[1] | bal[2] | bal[3]) != 0) {
+                int off = qn;
+                const uint32_t rv = (uint32_t)(v - s0) << 16;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (bal[k] != 0) {
+                        if ((bal[k] >> lane) & 1ull)
+                            queue[off + __popcll(bal[k] & lanes_below())] =
+                                make_uint2((uint32_t)(ub + k) | ((uint32_t)gxk[k] << 16),
+                                           ((uint32_t)gyk[k] & 0xffffu) | rv);
+                        off += __popcll(bal[k]);
+                    }
                 }
-                off += __popcll(p_bal[k]);
+                qn = off;
+                if (qn >= kEdgeFlushAt) flush();
             }
+            ++v;
+        };
+        while (v <= ve) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) LB[j] = load_row(v + 4 + j);
+            step(IntC<0>{}, LA[0]);
+            step(IntC<1>{}, LA[1]);
+            step(IntC<2>{}, LA[2]);
+            if (v > ve) break;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) LA[j] = load_row(v + 4 + j);
+            step(IntC<3>{}, LB[0]);
+            step(IntC<4>{}, LB[1]);
+            step(IntC<5>{}, LB[2]);
         }
-    };
-    for (int v = vs; v <= ve; ++v) {
-        const Row6 gn = load_row(v + 2);
-        load_raw(v + 1, rn);
-        const int vn = min(v + 1, ve);
-        const uint32_t lo_n = rb[2 * vn], hi_n = rb[2 * vn + 1];
-        const double vpy_n = tvpy[vn];
-        int xa[6], xm[6], xc[6];
-        unpack(ga, xa);
-        unpack(gm, xm);
-        unpack(gc, xc);
-        const bool vin = v >= 1 && v <= H - 2;
-        const double tt = (double)v - vpy;
-        uint32_t rec[4];
-        int binv[4];
-        uint64_t bal[4];
-        uint32_t emask = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int u = ub + k;
-            int gx = 0, gy = 0, bin = -1;
-            bool edge = false;
-            if (vin && u >= 1 && u <= W - 2 && rc[k] >= lo && rc[k] <= hi) {
-                gx = (xa[k + 2] - xa[k]) + 2 * (xm[k + 2] - xm[k]) + (xc[k + 2] - xc[k]);
-                gy = (xc[k] - xa[k]) + 2 * (xc[k + 1] - xa[k + 1]) + (xc[k + 2] - xa[k + 2]);
-                edge = gx * gx + gy * gy > t2;
-            }
-            if (edge && gx != 0) bin = vote_bin(tt, gy, gx, u, d.half, d.W2);
-            rec[k] = ((uint32_t)gx & 0xffffu) | ((uint32_t)gy << 16);
-            binv[k] = bin;
-            emask |= edge ? (1u << k) : 0u;
-            bal[k] = __ballot(edge);
-        }
-        const int tot = __popcll(bal[0]) + __popcll(bal[1]) + __popcll(bal[2]) + __popcll(bal[3]);
-        flush();                     // the previous row's records, after this row's work
-        p_v = v;
-        p_tot = tot;
-        p_mask = emask;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { p_rec[k] = rec[k]; p_bin[k] = binv[k]; p_bal[k] = bal[k]; }
-        if (tot > 0 && lane == 0) p_base = atomicAdd(&d.rowcnt[(int64_t)b * H + v], tot);
-        // this step's loads are complete before the next step on every path (vmcnt 0, the
-        // other counters untouched), so the next step's work never waits for its own loads
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-        ga = gm; gm = gc; gc = gn;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) rc[k] = rn[k];
-        lo = lo_n; hi = hi_n; vpy = vpy_n;
+        flush();
     }
-    flush();
+    __syncthreads();
+    if (t < rows) d.rowcnt[(int64_t)b * H + s0 + t] = scnt[t];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1282,8 +1326,6 @@ __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, dou
     const float w = sq ? expf(-(p * p) * inv_sg2) : expf(-p * inv_sg2);
     return (float)ed.gx * w;
 }
-
-template <int N> using IntC = std::integral_constant<int, N>;
 
 template <int NC, int NT>
 __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_mask, float* energy_out) {
@@ -2151,6 +2193,10 @@ size_t vpx_fit_lds(const Dev& d) {
     return sizeof(int) * (3 * WP + (size_t)d.H);
 }
 
+size_t edges_lds(int nwaves) {
+    return (sizeof(double) + 3 * sizeof(uint32_t)) * kEdgeStrip + sizeof(uint2) * kEdgeQueue * (size_t)nwaves;
+}
+
 size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 6); }
 
 // Raise a kernel's dynamic LDS limit once per size (later launches, including those recorded
@@ -2265,20 +2311,23 @@ void launch_hist(int npt, dim3 g, size_t lds, hipStream_t st, const Dev& d, cons
     else hipLaunchKernelGGL((k_vdisp_hist<FMT, 16>), g, dim3(kBlock), lds, st, d, dp, pitch, out);
 }
 
-ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t* sid, const int64_t* fidx,
-                    int32_t* vdisp_out, double* beta_out, hipStream_t st) {
+// S1 for the active frames of f
+ld_status run_hist(ld_frame f, const void* disp, int64_t pitch, int32_t* vdisp_out, hipStream_t st) {
     Dev& d = f->d;
     dim3 g1((d.H + d.hist_rows - 1) / d.hist_rows, f->active);
     const size_t l1 = sizeof(int) * d.hist_rows * d.D1;
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
-    {
-        ProfScope ps(f, 0, st);
-        const int npt = (d.W + kBlock - 1) / kBlock;
-        if (d.fmt == LD_DISP_U8) launch_hist<LD_DISP_U8>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
-        else if (d.fmt == LD_DISP_F32) launch_hist<LD_DISP_F32>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
-        else launch_hist<LD_DISP_U16Q4>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
-    }
-    if (launch_ok() != LD_OK) return LD_E_HIP;
+    ProfScope ps(f, 0, st);
+    const int npt = (d.W + kBlock - 1) / kBlock;
+    if (d.fmt == LD_DISP_U8) launch_hist<LD_DISP_U8>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
+    else if (d.fmt == LD_DISP_F32) launch_hist<LD_DISP_F32>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
+    else launch_hist<LD_DISP_U16Q4>(npt, g1, l1, st, d, dp, pitch, vdisp_out);
+    return launch_ok();
+}
+
+// S2-S3 for the active frames of f
+ld_status run_vdisp_fit(ld_frame f, const uint64_t* sid, const int64_t* fidx, double* beta_out, hipStream_t st) {
+    Dev& d = f->d;
     const size_t l2 = vdisp_fit_lds(d);
     allow_lds(k_vdisp_fit, l2);
     {
@@ -2288,19 +2337,29 @@ ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t*
     return launch_ok();
 }
 
+ld_status run_vdisp(ld_frame f, const void* disp, int64_t pitch, const uint64_t* sid, const int64_t* fidx,
+                    int32_t* vdisp_out, double* beta_out, hipStream_t st) {
+    const ld_status s = run_hist(f, disp, pitch, vdisp_out, st);
+    return s == LD_OK ? run_vdisp_fit(f, sid, fidx, beta_out, st) : s;
+}
+
 ld_status run_edges(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dpt, hipStream_t st) {
     Dev& d = f->d;
-    dim3 g3((d.W + 4 * kQT - 1) / (4 * kQT), (d.H + kEdgeRows - 1) / kEdgeRows, f->active);
+    const int nw = (d.W + kEdgeCols - 1) / kEdgeCols;
+    dim3 g3((d.H + kEdgeStrip - 1) / kEdgeStrip, f->active);
+    const size_t lds = edges_lds(nw);
     const uint8_t* dp = static_cast<const uint8_t*>(disp);
     ProfScope ps(f, 2, st);
-    const uint32_t* rbd = d.rbound;
-    const double* tabd = d.tab;
-    if (d.fmt == LD_DISP_U8)
-        hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
-    else if (d.fmt == LD_DISP_F32)
-        hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
-    else
-        hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(kQT), 0, st, d, grey, gp, dp, dpt, rbd, tabd);
+    if (d.fmt == LD_DISP_U8) {
+        allow_lds(k_edges<LD_DISP_U8>, lds);
+        hipLaunchKernelGGL(k_edges<LD_DISP_U8>, g3, dim3(nw * kWave), lds, st, d, grey, gp, dp, dpt);
+    } else if (d.fmt == LD_DISP_F32) {
+        allow_lds(k_edges<LD_DISP_F32>, lds);
+        hipLaunchKernelGGL(k_edges<LD_DISP_F32>, g3, dim3(nw * kWave), lds, st, d, grey, gp, dp, dpt);
+    } else {
+        allow_lds(k_edges<LD_DISP_U16Q4>, lds);
+        hipLaunchKernelGGL(k_edges<LD_DISP_U16Q4>, g3, dim3(nw * kWave), lds, st, d, grey, gp, dp, dpt);
+    }
     return launch_ok();
 }
 
@@ -2382,7 +2441,8 @@ ld_status check_images(ld_frame f, const uint8_t* grey, int64_t gp, const void* 
     const Dev& d = f->d;
     const int es = elem_size(d.fmt);
     if (disp == nullptr || dpt < (int64_t)d.W * es || dpt % es != 0 || !aligned(disp, es)) return LD_E_INVAL;
-    if (grey != nullptr && gp < d.W) return LD_E_INVAL;
+    // the edge kernel addresses a frame's grey rows with 32-bit offsets
+    if (grey != nullptr && (gp < d.W || (int64_t)d.H * gp > (int64_t)INT32_MAX - 4096)) return LD_E_INVAL;
     return LD_OK;
 }
 

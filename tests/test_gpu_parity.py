@@ -289,3 +289,52 @@ def test_batch_invariance_and_determinism():
         assert a["lanes"][k].tobytes() == b["lanes"][k].tobytes()
     assert np.array_equal(a["frames"][2]["energy"], one["frames"][0]["energy"])
     assert a["lanes"][2].tobytes() == one["lanes"][0].tobytes()
+
+
+def test_repeated_vp_ransac_equals_one_call():
+    """ld_vp_ransac may be called again on a frame object (after ld_vdisp, after ld_detect):
+    every call rebuilds the edge buckets and their counts, so the state after any such
+    sequence equals the state after one call."""
+    ld = _ld()
+    greys, disps, _ = synth.make_batch("c2", 4, 2)
+    B, H, W = greys.shape
+    det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
+    g, d = torch.from_numpy(greys).cuda(), torch.from_numpy(disps).cuda()
+    seed = torch.full((B, 5), float("nan"), dtype=torch.float64, device="cuda")
+    seed[:, 0] = 600.0
+    seed[:, 1:] = 0.0
+
+    def state():
+        det.sync()
+        out = []
+        for b in range(B):
+            rc = det.read(ld.LD_STATE_ROWCOUNT, b)
+            e = det.read(ld.LD_STATE_EDGES, b).reshape(H, W)
+            rows = [np.sort(e[v, : rc[v]].view(np.uint64)) for v in range(H)]
+            out.append((rc.copy(), rows, det.read(ld.LD_STATE_GAMMA, b).tobytes(),
+                        det.read(ld.LD_STATE_TABLES, b).tobytes(), det.read(ld.LD_STATE_ENERGY, b).tobytes()))
+        return out
+
+    def same(x, y):
+        for a, b in zip(x, y):
+            assert np.array_equal(a[0], b[0])
+            assert all(np.array_equal(p, q) for p, q in zip(a[1], b[1]))
+            assert a[2:] == b[2:]
+
+    det.vdisp(d)
+    det.vp_ransac(g, d)
+    det.lane_energy()
+    once = state()
+    assert once[0][0].sum() > 0
+    det.vdisp(d)
+    det.vp_ransac(g, d, seed_gamma=seed)
+    det.vp_ransac(g, d)
+    det.vp_ransac(g, d)
+    det.lane_energy()
+    same(once, state())
+    lanes = det.lanes_buffer()
+    det.detect(g, d, lanes)
+    det.vp_ransac(g, d)
+    det.lane_energy()
+    same(once, state())
+    det.close()
