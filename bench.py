@@ -2,9 +2,12 @@
 
 One step = ld_detect over a batch of synthetic 1242x375 frames already resident in HBM
 (grey u8 + f32 subpixel disparity, 4 curved lanes, ~10% obstacle pixels, 16 sequences of
-64 frames).  Prints one JSON line: frames/s, ms per step, the roofline of the dominant
-kernel (HIP events on the launch stream), single-frame latency p50/p99, and the CPU oracle
-timed on the host's cores on a bounded sample of the same frames.
+64 frames).  Prints one JSON line: frames/s and ms per step (timed with no per-kernel
+events), the roofline of the dominant kernel (its algorithmic bytes or operations per launch
+over its average launch time, HIP events on the launch stream, in a separate pass), the
+whole path's fraction of the HBM roofline, other batch sizes, the 1920x1080 u16 throughput
+stream, single-frame latency p50/p99, the learned-pruned path, a serving run, and the CPU
+oracle timed on the host's cores (one core and all cores, median of five runs each).
 """
 from __future__ import annotations
 
@@ -158,17 +161,10 @@ def learned_leg(args, det, g, d, lanes, plain_lanes, tgreys, tdisps, plain_ms):
     del G, D
     log(f"trained {args.train_steps} steps in {train_s:.1f}s, loss {losses[:10].mean():.4f} -> {losses[-10:].mean():.4f}")
     lp = det.lanes_buffer()
-    for _ in range(args.warmup):
-        det.detect_pruned(net, g, d, lp)
-    torch.cuda.synchronize()
-    det.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    ms = time_steps(lambda: det.detect_pruned(net, g, d, lp), args.steps, args.warmup)
+    det.profile(True)                  # kernel times in a pass of their own
     for _ in range(args.steps):
         det.detect_pruned(net, g, d, lp)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
     kt = det.kernel_times()
     det.profile(False)
     L = ld.Detector.parse_lanes(lp)
@@ -194,29 +190,143 @@ def learned_leg(args, det, g, d, lanes, plain_lanes, tgreys, tdisps, plain_ms):
     return res, net
 
 
-def cpu_baseline(greys, disps, seconds: float, threads: int):
-    """The oracle, as it stands, on the host cores: frames split over `threads` threads
-    (ctypes releases the GIL during each call)."""
+def host_cores():
+    """Cores this process may run on: the affinity set, capped by the cgroup CPU quota."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()
+        if q != "max":
+            n = max(1, min(n, int(int(q) // int(per))))
+    except (OSError, ValueError):
+        pass
+    return n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(greys, disps, seconds: float):
+    """The oracle, as it stands, on the host cores: one core (frames in sequence) and all
+    cores (one thread per core, frames split over the threads; ctypes releases the GIL during
+    each call).  Each figure is the median of five runs over a bounded sample of the timed
+    workload, sized so that the ten runs take about `seconds` of wall time."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
     oracle.lib()
+    oracle.detect(greys[0], disps[0], 128)               # warm-up (page-in, library load)
     t0 = time.perf_counter()
-    oracle.detect(greys[0], disps[0], 128)
-    per_frame = time.perf_counter() - t0
-    n = int(max(threads, min(len(greys), seconds / max(per_frame, 1e-3))))
-    idx = list(range(n))
+    oracle.detect(greys[1], disps[1], 128, frame_idx=1)
+    t1 = time.perf_counter() - t0
+    cores = host_cores()
+    per_run = max(1, int(seconds / 10 / t1))             # frames one core does in one run
+    one, allc = [], []
+    for r in range(5):
+        idx = [(r * per_run + i) % len(greys) for i in range(per_run)]
+        t0 = time.perf_counter()
+        for i in idx:
+            oracle.detect(greys[i], disps[i], 128, frame_idx=i)
+        one.append(len(idx) / (time.perf_counter() - t0))
+    n_all = per_run * cores
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        for r in range(5):
+            idx = [(r * n_all + i) % len(greys) for i in range(n_all)]
+            t0 = time.perf_counter()
+            list(ex.map(lambda i: oracle.detect(greys[i], disps[i], 128, frame_idx=i), idx))
+            allc.append(len(idx) / (time.perf_counter() - t0))
+    return {"value": float(np.median(allc)), "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"median of 5 runs of {n_all} frames of the 1242x375 workload on {cores} threads "
+                      f"(one per core); single core: median of 5 runs of {per_run} frames in sequence",
+            "single_core": {"value": float(np.median(one)), "unit": "frames/s", "cores": 1,
+                            "ms_per_frame": 1e3 / float(np.median(one))},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
-    def work(i):
-        oracle.detect(greys[i], disps[i], 128, frame_idx=i)
-        return i
 
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(work, idx))
-    wall = time.perf_counter() - t0
-    return {"value": n / wall, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} frames of the 1242x375 workload, {threads} threads, {wall:.1f} s wall",
-            "single_thread_ms_per_frame": per_frame * 1e3}
+# Algorithmic work per frame of each kernel, for its roofline (units: bytes for "hbm", 32-bit
+# lane operations for "alu").  The HBM figures are the compulsory reads of the input images
+# (the disparity once for the histogram, the grey image once for the gradient); the kernels
+# between them move only intermediates, priced at zero bytes, and are bound by their
+# arithmetic instead.
+def kernel_work(k, W, H, R, es, p):
+    N = W * H
+    if k == "k_vdisp_hist":
+        return "hbm", N * es, f"{N * es} B per frame (disparity read once)"
+    if k == "k_edges":
+        return "hbm", N * 1, f"{N} B per frame (grey read once)"
+    if k == "k_vpx_fit":
+        ops = R * 2 * W * (2 * p.tau_x_max + 1) * 2
+        return "alu", ops, f"{ops:.4g} ops per frame (row DP: R x 2W x 11 taps x add+min)"
+    if k == "k_energy":
+        ops = R * (W * 16 + 2 * W * 6)
+        return "alu", ops, (f"{ops:.4g} ops per frame (per road row: 16 per pixel for q scatter, 7-row and 3-column "
+                            f"box sums and M_1; 6 per candidate for the track fma, rounding, range test, gather-add)")
+    if k == "k_vdisp_fit":
+        ops = (128 + 1) * H * (p.tau_y_max + 1) * 2
+        return "alu", ops, f"{ops:.4g} ops per frame (v-disparity DP: D x H x 7 taps x add+min)"
+    if k == "k_vpx_ransac":
+        ops = R * 64 * 2 * 16
+        return "alu", ops, f"{ops:.4g} ops per frame (64 quartic hypotheses x R points x ~16 ops, two rounds)"
+    ops = 2 * W * 4
+    return "alu", ops, f"{ops:.4g} ops per frame (2W candidates x compare/select)"
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def c3_leg(args):
+    """Throughput stream of 1920x1080 frames: u16 disparity in 1/16 px up to 255 px, 6 lanes
+    (inner 4 dashed), 15% obstacle pixels, grey gain redrawn every 50 frames.  `c3_distinct`
+    frames are generated and tiled to `c3_frames` (each position keeps its own frame index,
+    hence its own RANSAC draws)."""
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1807_02752_amd import ld
+    n = args.c3_distinct
+    jobs = [(0, i, min(10, n - i)) for i in range(0, n, 10)]
+    with ProcessPoolExecutor(max_workers=args.procs) as ex:
+        parts = list(ex.map(_gen_c3, jobs))
+    greys = np.concatenate([q[0] for q in parts])
+    disps = np.concatenate([q[1] for q in parts])
+    reps = (args.c3_frames + n - 1) // n
+    g = torch.from_numpy(greys).cuda().repeat(reps, 1, 1)[: args.c3_frames].contiguous()
+    d = torch.from_numpy(disps).cuda().repeat(reps, 1, 1)[: args.c3_frames].contiguous()
+    del greys, disps
+    B, H, W = g.shape
+    det = ld.Detector(W, H, B, ld.LD_DISP_U16Q4, 255)
+    lanes = det.lanes_buffer()
+    ms = time_steps(lambda: det.detect(g, d, lanes), max(2, args.steps // 4), 1)
+    L = ld.Detector.parse_lanes(lanes)
+    det.close()
+    fps = B / (ms / 1e3)
+    alg = W * H * 3
+    return {"workload": f"{B} frames 1920x1080, u16 disparity (1/16 px, d_max 255), 6 lanes, 15% obstacles, gain "
+                        f"changes every 50 frames ({n} generated, tiled)", "frames_per_step": B,
+            "value": fps, "unit": "frames/s", "ms_per_step": ms, "alg_bytes_per_frame": alg,
+            "hbm_frac": alg * fps / (HBM_PEAK_GBS * 1e9), "lanes_per_frame": float(L["n"].mean())}
+
+
+def _gen_c3(args):
+    from paper_1807_02752_amd import synth
+    seed, start, count = args
+    g, d, _ = synth.make_batch("c3", seed, count, start)
+    return g, d
 
 
 def main():
@@ -232,6 +342,8 @@ def main():
     ap.add_argument("--procs", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--train-steps", type=int, default=300, help="training steps of the pruning network (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0, help="length of the serving run (0: skip)")
+    ap.add_argument("--c3-frames", type=int, default=1000, help="frames of the 1920x1080 stream (0: skip)")
+    ap.add_argument("--c3-distinct", type=int, default=250, help="distinct 1920x1080 frames generated")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (4 launches) to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -268,58 +380,48 @@ def main():
     d = torch.from_numpy(disps).to(dev)
     det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
     lanes = det.lanes_buffer()
-    for _ in range(args.warmup):
-        det.detect(g, d, lanes)
-    torch.cuda.synchronize()
-    log("warmup done")
 
-    det.profile(True)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        det.detect(g, d, lanes)
-    stop.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    ktimes = det.kernel_times()
-    det.profile(False)
-    ms_per_step = total_ms / args.steps
-    fps = B * args.steps / (total_ms / 1e3)
+    # headline: whole steps with no per-kernel events
+    ms_per_step = time_steps(lambda: det.detect(g, d, lanes), args.steps, args.warmup)
+    fps = B / (ms_per_step / 1e3)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, {fps:.0f} frames/s")
 
-    # per-kernel averages and the dominant kernel's roofline
+    # per-kernel launch times in a separate pass (HIP events on the launch stream)
+    det.profile(True)
+    for _ in range(args.steps):
+        det.detect(g, d, lanes)
+    ktimes = det.kernel_times()
+    det.profile(False)
     lanes_np = ld.Detector.parse_lanes(lanes)
     infos = np.stack([det.read(ld.LD_STATE_INFO, b) for b in range(min(B, 64))])
     R_mean = float(infos[:, 6].mean())
-    kern = {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": int(v[1])} for k, v in ktimes.items()}
+    kern = {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": int(v[1])} for k, v in ktimes.items() if v[1]}
     dom = max(kern, key=lambda k: kern[k]["ms_per_launch"])
     t_dom = kern[dom]["ms_per_launch"] / 1e3
     p = det.params
-    if dom == "k_vdisp_hist":
-        per_unit, units = W * H * 4, B
-        roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                "achieved": per_unit * units / t_dom / 1e9, "per_unit": f"{per_unit} B per frame (disparity read)"}
-    elif dom == "k_edges":
-        per_unit = (R_mean + 2) * W * 1 + R_mean * W * 4
-        roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                "achieved": per_unit * B / t_dom / 1e9, "per_unit": f"{per_unit:.0f} B per frame (road rows of grey + disparity)"}
-    elif dom == "k_vpx_fit":
-        ops = R_mean * 2 * W * (2 * p.tau_x_max + 1) * 2
-        roof = {"bound": "alu", "unit": "TOP/s", "peak": ALU_PEAK_TOPS, "achieved": ops * B / t_dom / 1e12,
-                "per_unit": f"{ops:.3g} ops per frame (row DP: R x 2W x 11 taps x add+min)"}
-    elif dom == "k_energy":
-        ops = R_mean * (W * 16 + 2 * W * 6)
-        roof = {"bound": "alu", "unit": "TOP/s", "peak": ALU_PEAK_TOPS, "achieved": ops * B / t_dom / 1e12,
-                "per_unit": f"{ops:.3g} ops per frame (M_0/M_1 rows + 2W track gathers per road row)"}
-    else:   # k_vdisp_fit / k_peaks
-        ops = (128 + 1) * H * (p.tau_y_max + 1) * 2
-        roof = {"bound": "alu", "unit": "TOP/s", "peak": ALU_PEAK_TOPS, "achieved": ops * B / t_dom / 1e12,
-                "per_unit": f"{ops:.3g} ops per frame (v-disparity DP: D x H x 7 taps x add+min)"}
-    roof["kernel"] = dom
+    bound, per_unit, desc = kernel_work(dom, W, H, R_mean, 4, p)
+    if bound == "hbm":
+        roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": per_unit * B / t_dom / 1e9}
+    else:
+        roof = {"bound": "alu", "unit": "TOP/s", "peak": ALU_PEAK_TOPS, "achieved": per_unit * B / t_dom / 1e12}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(dom)
-    roof["launch_ms"] = kern[dom]["ms_per_launch"]
+    roof.update({"kernel": dom, "per_unit": desc, "units_per_launch": B, "launch_ms": kern[dom]["ms_per_launch"]})
+    per_kernel_roof = {}
+    for k, v in kern.items():
+        bnd, pu, _ = kernel_work(k, W, H, R_mean, 4, p)
+        t = v["ms_per_launch"] / 1e3
+        ach = pu * B / t / (1e9 if bnd == "hbm" else 1e12)
+        per_kernel_roof[k] = {"ms": round(v["ms_per_launch"], 4), "bound": bnd,
+                              "frac": round(ach / (HBM_PEAK_GBS if bnd == "hbm" else ALU_PEAK_TOPS), 4)}
+
+    # other batch sizes (the first frames of the same workload)
+    batches = {}
+    for nb in (64, 256):
+        det.set_active(nb)
+        ms = time_steps(lambda: det.detect(g, d, lanes), args.steps, 2)
+        batches[str(nb)] = {"ms_per_step": ms, "frames_per_s": nb / (ms / 1e3)}
+    det.set_active(B)
 
     # single-frame latency (batch of one, synchronous per frame)
     lat = []
@@ -337,6 +439,7 @@ def main():
         det1.close()
 
     alg_bytes = W * H * (1 + 4)
+    path_achieved = alg_bytes * fps / 1e9
     out = {
         "metric": METRIC, "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -345,24 +448,34 @@ def main():
                                "16 sequences x 64 frames", "frames_per_step": B, "width": W, "height": H, "d_max": 128,
                    "variant": "plain"},
         "roofline": roof,
-        "hbm_frac": alg_bytes * fps / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac": path_achieved / HBM_PEAK_GBS,
+        "roofline_path": {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": path_achieved,
+                          "frac": path_achieved / HBM_PEAK_GBS,
+                          "per_unit": f"{alg_bytes} B per frame (grey once + f32 disparity once)"},
+        "kernels": per_kernel_roof,
+        "batch_sizes": batches,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "batch": 1},
-        "kernels_ms_per_launch": {k: round(v["ms_per_launch"], 4) for k, v in kern.items()},
         "road_rows_mean": R_mean,
         "lanes_per_frame": float(lanes_np["n"].mean()),
         "learned_pruned": None,
     }
+    det.close()
+    det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
     net = None
     if args.train_steps > 0:
         out["learned_pruned"], net = learned_leg(args, det, g, d, lanes, lanes_np, tgreys, tdisps, ms_per_step)
+    det.close()
+    del g, d
+    torch.cuda.empty_cache()
+    if args.c3_frames > 0:
+        out["c3_stream"] = c3_leg(args)
+        torch.cuda.empty_cache()
     if serve_pool is not None:
         out["serving"] = serving_leg(args, serve_pool, net)
     if net is not None:
         net.close()
     if not args.no_cpu:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(greys, disps, args.cpu_seconds, threads)
-    det.close()
+        out["cpu_baseline"] = cpu_baseline(greys, disps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
