@@ -364,11 +364,13 @@ __device__ void ransac_block(const int* X, const int* Y, int n0, int* cur, int* 
 // S1: v-disparity histogram m_y(d, v) (Sec. 2.2).  A workgroup bins hist_rows rows of one
 // frame into LDS; within a wave, the lanes that share the first active lane's bin are merged
 // by ballot into one LDS atomic and the other lanes add directly (a road row puts most
-// pixels into one or two bins, so one merge removes most of the same-address traffic).  Rows
+// pixels into one or two bins, so one merge removes most of the same-address traffic; merging
+// two or three bins this way measured slower).  Rows
 // are taken four at a time, and the raw values of the next four rows are loaded while the
 // current four are binned, so a wave always has a group of loads in flight.  The counts
 // leave transposed, hist_rows consecutive rows per disparity.
 constexpr int kHistGroup = 4;
+constexpr int kHistMerge = 1;
 
 template <int FMT> struct RawPixel { using T = uint8_t; };
 template <> struct RawPixel<LD_DISP_F32> { using T = float; };
@@ -436,17 +438,24 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* dis
         for (int r = 0; r < kHistGroup; ++r) {
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
-                const bool valid = ok[r][k];
+                bool pend = ok[r][k];
                 const int bin = bins[r][k];
-                const uint64_t act = __ballot(valid);
-                if (act) {
+                int* hrow = hist + (g + r) * D1;
+                uint64_t act = __ballot(pend);
+                // up to kHistMerge distinct bins of the wave are merged, each into one atomic
+                // by its first lane; the lanes left over (many distinct bins) add one each
+#pragma unroll
+                for (int it = 0; it < kHistMerge; ++it) {
+                    if (act == 0) break;
                     const int leader = __ffsll((unsigned long long)act) - 1;
                     const int b0 = __builtin_amdgcn_readlane(bin, leader);   // uniform: no LDS round trip
-                    const bool same = valid && bin == b0;
+                    const bool same = pend && bin == b0;
                     const uint64_t m = __ballot(same);
-                    if (lane == leader) atomicAdd(&hist[(g + r) * D1 + b0], __popcll(m));
-                    if (valid && !same) atomicAdd(&hist[(g + r) * D1 + bin], 1);
+                    if (lane == leader) atomicAdd(&hrow[b0], __popcll(m));
+                    pend = pend && !same;
+                    act &= ~m;
                 }
+                if (act != 0 && pend) atomicAdd(&hrow[bin], 1);
             }
         }
     }
@@ -1305,14 +1314,17 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
 // along its track (Eq. lane_energy, Eq. lane_visualisation).
 //
 // One workgroup per frame.  First q is computed for every road edge (each wave a group of rows)
-// into a per-edge buffer.  Then the road rows are swept upwards: q row v-4 is scattered into a zeroed
-// LDS row, every thread pushes its NC columns into a 9-row register ring (rows v-4..v+4) and
-// forms V(x, v) = sum_y s_y C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0
-// outside the image; after a barrier the column owners form the row of
-// M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) (terms outside the image dropped) in one
-// of two LDS rows, and every candidate adds M_1 at its track column one row later, so a row
-// costs two barriers.  The row loop is unrolled nine times so that the ring rotates by
-// renaming registers instead of moving them.
+// into a per-edge buffer.  Then the road rows are swept upwards.  At the step of row v every
+// thread pushes its NC columns of the dense q row v-4 (scattered into LDS during the previous
+// step) into a 9-row register ring (rows v-4..v+4) and forms V(x, v) = sum_y s_y C(x, v+y),
+// C = vertical 7-row sums, with the zero padding of M_0 outside the image, while the edges of
+// row v-5 are scattered into the other q row; after the step's one barrier the column owners
+// form M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) (terms outside the image dropped)
+// into one of two LDS rows, and every candidate adds M_1 at its track column of row v+1.  The
+// q, V and M_1 rows are double-buffered by row parity, so one barrier per row orders every
+// write before its reads.  Rows are padded to the NC * 256 columns the threads own (the
+// columns past W hold zeros), so the column loops carry no bounds test.  The row loop is
+// unrolled nine times so that the ring rotates by renaming registers instead of moving them.
 __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
     const double tx = (double)(-ed.gy), ty = (double)ed.gx;
     const double rx = vx - (double)ed.u, ry = vy - (double)r;
@@ -1342,11 +1354,12 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         }
         return;
     }
-    float* qb0 = fsm;                // W, dense q row (ping)
-    float* qb1 = qb0 + W;            // W, dense q row (pong)
-    float* Vp = qb1 + W;             // W + 4: V row with two zero columns on each side
-    float* mb0 = Vp + W + 4;         // W + 1, M_1 row of even v (entry W stays 0)
-    float* mb1 = mb0 + W + 1;        // W + 1, M_1 row of odd v (entry W stays 0)
+    constexpr int WP = NC * kBlock;  // columns owned by the threads (>= W)
+    // by row parity: dense q rows; V rows, column u at u + 2 (two zero columns each side); M_1
+    // rows (entries >= W stay 0)
+    auto qb = [&](int par) -> float* { return fsm + par * WP; };
+    auto Vp = [&](int par) -> float* { return fsm + 2 * WP + par * (WP + 4); };
+    auto mb = [&](int par) -> float* { return fsm + 4 * WP + 8 + par * (WP + 1); };
     const double* tf = d.tab + (int64_t)b * 6 * H;
     const double* tvpy = tf + 2 * H;
     const double* tvpx = tf + 3 * H;
@@ -1385,7 +1398,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
                 qbuf[(int64_t)r * W + i] = edge_q(edges[(int64_t)r * W + i], r, vx[j], vy[j], inv_sg2, sq);
         }
     }
-    for (int i = t; i < 5 * W + 6; i += kBlock) fsm[i] = 0.0f;
+    for (int i = t; i < 6 * WP + 10; i += kBlock) fsm[i] = 0.0f;
     float ring[NC][9];
 #pragma unroll
     for (int k = 0; k < NC; ++k)
@@ -1402,12 +1415,6 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     }
     __syncthreads();
 
-    auto scatter = [&](int r, float* qb) {
-        if (r >= v_h && r <= v_max) {
-            const int cnt = rowcnt[r];
-            for (int i = t; i < cnt; i += kBlock) qb[edges[(int64_t)r * W + i].u] = qbuf[(int64_t)r * W + i];
-        }
-    };
     // the next row to scatter: its count and each thread's first edge are loaded a step ahead
     // (from a clamped, always valid index; the count masks them when they are used)
     int nx_r = -1, nx_cnt = 0, nx_u = 0;
@@ -1419,19 +1426,19 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         nx_u = edges[(int64_t)rr * W + i].u;
         nx_q = qbuf[(int64_t)rr * W + i];
     };
-    auto scatter_next = [&](float* qb) {
-        if (t < nx_cnt) qb[nx_u] = nx_q;
+    auto scatter_next = [&](float* q) {
+        if (t < nx_cnt) q[nx_u] = nx_q;
         for (int i = t + kBlock; i < nx_cnt; i += kBlock)
-            qb[edges[(int64_t)nx_r * W + i].u] = qbuf[(int64_t)nx_r * W + i];
+            q[edges[(int64_t)nx_r * W + i].u] = qbuf[(int64_t)nx_r * W + i];
     };
-    // slot S of the ring takes the newest row; reads and re-zeroes the owned columns of qb
-    auto push = [&](auto Sc, float* qb) {
+    // slot S of the ring takes the newest row; reads and re-zeroes the owned columns of q
+    auto push = [&](auto Sc, float* q) {
         constexpr int S = decltype(Sc)::value;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
-            ring[k][S] = 0.0f;
-            if (u < W) { ring[k][S] = qb[u]; qb[u] = 0.0f; }
+            ring[k][S] = q[u];
+            q[u] = 0.0f;
         }
     };
     // the track of every live candidate moves to row w and adds M_1(col, w); a track outside
@@ -1445,63 +1452,67 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         cA = upd ? tA[w] : 0.0;
         cB = upd ? tB[w] : 1.0;
     };
-    auto candidates = [&](int w, const float* m1row) {
+    auto candidates = [&](const float* m1row) {
         const double A = cA, Bc = cB;
-        (void)w;
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             uu[k] = fma(Bc, uu[k], A);
             const int c = (int)floor(uu[k] + 0.5);
-            const bool in = live[k] && (unsigned)c < (unsigned)W;
+            const bool in = live[k] & ((unsigned)c < (unsigned)W);   // no branch: both are computed
             ee[k] += (double)m1row[in ? c : W];
         }
     };
-    // rows v_max .. v_max-3 enter slots 0, 8, 7, 6; rows below the image stay zero
-    scatter(v_max, qb0);     __syncthreads(); push(IntC<0>{}, qb0);
-    scatter(v_max - 1, qb1); __syncthreads(); push(IntC<8>{}, qb1);
-    scatter(v_max - 2, qb0); __syncthreads(); push(IntC<7>{}, qb0);
-    scatter(v_max - 3, qb1); __syncthreads(); push(IntC<6>{}, qb1);
+    // rows v_max .. v_max-3 enter slots 0, 8, 7, 6; rows below the image stay zero; row
+    // v_max-4 waits in its q row for the first step
+    prefetch(v_max);
+    scatter_next(qb(v_max & 1));               __syncthreads(); push(IntC<0>{}, qb(v_max & 1));
+    prefetch(v_max - 1);
+    scatter_next(qb((v_max - 1) & 1));         __syncthreads(); push(IntC<8>{}, qb((v_max - 1) & 1));
+    prefetch(v_max - 2);
+    scatter_next(qb((v_max - 2) & 1));         __syncthreads(); push(IntC<7>{}, qb((v_max - 2) & 1));
+    prefetch(v_max - 3);
+    scatter_next(qb((v_max - 3) & 1));         __syncthreads(); push(IntC<6>{}, qb((v_max - 3) & 1));
     prefetch(v_max - 4);
+    scatter_next(qb((v_max - 4) & 1));
+    prefetch(v_max - 5);
+    __syncthreads();
     int v = v_max;
     // one row: newest ring slot S holds row v-4, slot (S + j) % 9 row v-4+j
     auto step = [&](auto Sc) -> bool {
         constexpr int S = decltype(Sc)::value;
         if (v < v_end) return false;
-        float* qb = ((v_max - v) & 1) ? qb1 : qb0;
-        scatter_next(qb);              // row v - 4
-        prefetch(v - 5);
-        __syncthreads();
-        push(Sc, qb);
+        const int par = v & 1;
+        push(Sc, qb(par));               // row v - 4 (same parity as v)
+        const bool up = v >= 1, dn = v + 1 <= v_max;   // M_0 is zero outside the image rows
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
-            if (u < W) {
-                float r[9];
+            float r[9];
 #pragma unroll
-                for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
-                const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
-                const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
-                const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
-                const float cp1 = (s5 + r[7]) + r[8];   // C(v+1): rows v-2..v+4
-                float V = 2.0f * c0;
-                if (v >= 1) V += cm1;                   // M_0 is zero outside the image rows
-                if (v + 1 <= v_max) V += cp1;
-                Vp[u + 2] = V;
-            }
+            for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
+            const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
+            const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
+            const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
+            const float cp1 = (s5 + r[7]) + r[8];   // C(v+1): rows v-2..v+4
+            float V = 2.0f * c0;
+            V += up ? cm1 : 0.0f;
+            V += dn ? cp1 : 0.0f;
+            Vp(par)[u + 2] = V;
         }
+        scatter_next(qb(par ^ 1));       // row v - 5
+        prefetch(v - 6);
         __syncthreads();
-        float* mrow = (v & 1) ? mb1 : mb0;
+        float* mrow = mb(par);
+        const float* vr = Vp(par);
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             const int u = t + k * kBlock;
-            if (u < W) {
-                float m1 = 0.0f;
-                if (u + 1 <= W - 1) m1 += (Vp[u + 2] + Vp[u + 3]) + Vp[u + 4];
-                if (u >= 1) m1 -= (Vp[u] + Vp[u + 1]) + Vp[u + 2];
-                mrow[u] = m1;
-            }
+            const float g1 = (vr[u + 2] + vr[u + 3]) + vr[u + 4];   // columns u .. u+2 (M_0 at u+1)
+            const float g2 = (vr[u] + vr[u + 1]) + vr[u + 2];       // columns u-2 .. u (M_0 at u-1)
+            const float m1 = (u + 1 <= W - 1 ? g1 : 0.0f) - (u >= 1 ? g2 : 0.0f);
+            mrow[u] = u < W ? m1 : 0.0f;
         }
-        if (v < v_max) candidates(v + 1, ((v + 1) & 1) ? mb1 : mb0);
+        if (v < v_max) candidates(mb(par ^ 1));   // row v + 1
         coef(v);                       // for this row's candidates in the next step
         --v;
         return true;
@@ -1511,7 +1522,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     }
     if (v_end <= v_max) {
         __syncthreads();
-        candidates(v_end, (v_end & 1) ? mb1 : mb0);
+        candidates(mb(v_end & 1));
     }
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -2197,7 +2208,7 @@ size_t edges_lds(int nwaves) {
     return (sizeof(double) + 3 * sizeof(uint32_t)) * kEdgeStrip + sizeof(uint2) * kEdgeQueue * (size_t)nwaves;
 }
 
-size_t energy_lds(const Dev& d) { return sizeof(float) * (5 * (size_t)d.W + 6); }
+size_t energy_lds(int nc) { return sizeof(float) * (6 * (size_t)nc * kBlock + 10); }
 
 // Raise a kernel's dynamic LDS limit once per size (later launches, including those recorded
 // into a captured graph, issue nothing but the launch).
@@ -2409,7 +2420,7 @@ ld_status run_vp(ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, 
 
 template <int NC, int NT>
 void launch_energy(ld_frame f, const Dev& d, const uint8_t* mask, float* eout, hipStream_t st) {
-    const size_t l = energy_lds(d);
+    const size_t l = energy_lds(NC);
     allow_lds(k_energy<NC, NT>, l);
     hipLaunchKernelGGL((k_energy<NC, NT>), dim3(f->active), dim3(kBlock), l, st, d, mask, eout);
 }
