@@ -303,6 +303,18 @@ ld_status ld_cnn_destroy(ld_cnn n);
 ld_status ld_cnn_set_params(ld_cnn n, const float* params);
 ld_status ld_cnn_get_params(ld_cnn n, float* params);
 
+/* Checkpoint (training resume).  ld_cnn_save writes, synchronously, one header line of JSON
+ *   {"format": "ld_cnn_checkpoint", "version": 1, "params": 3057, "step": <Adam steps taken>,
+ *    "dtype": "float32", "arrays": ["master", "adam_m", "adam_v"], "config": {...the ld_cnn_config}}
+ * followed by the FP32 master weights, the Adam first and second moments (LD_CNN_PARAMS
+ * little-endian float32 each, in that order).  ld_cnn_load creates a network on the current
+ * device from such a file: weights, moments and step restored, so the next ld_cnn_train_step
+ * continues the run exactly; the configuration is the file's, or *cfg when cfg is not NULL.
+ * LD_E_INVAL for a file that cannot be opened or written, or whose header, parameter count or
+ * size does not match (checked before any device call). */
+ld_status ld_cnn_save(ld_cnn n, const char* path);
+ld_status ld_cnn_load(const char* path, const ld_cnn_config* cfg, ld_cnn* out);
+
 /* Network decisions for the active frames of f into f's band buffer (needs ld_vdisp on f;
  * LD_E_STATE otherwise).  prob_out: nullable device float batch x n_bands x 16 x width,
  * sigmoid(z) (0 where a frame has no band).  The frame format must have varpi > 0. */
@@ -339,6 +351,9 @@ ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t g
  *     a_v = B_v a_{v+1}, b_v = fma(B_v, b_{v+1}, A_v), column floor(u_v + 0.5), meets a
  *     marking pixel; kept candidates are dilated by `dilate`;
  *  5. energies of the kept candidates (0 for the others) and peaks.
+ * seed_gamma (nullable device n x 5, as in ld_vp_ransac: a stream's previous fit) is hypothesis 0
+ * of the V_px RANSAC of every frame for which step 2 drew no seed line (seed_ransac off, or a
+ * fallback frame).
  * Fallback to the plain search (LD_FLAG_FALLBACK) for a frame: no seed (fewer than
  * min_votes marking votes, or a frame narrower than 128 columns), or the window path
  * touches an inner window edge -> plain
@@ -346,7 +361,7 @@ ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t g
  * energies of every candidate and peaks again. */
 ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                            int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
-                           ld_lanes* lanes_out, float* curves_out, void* hip_stream);
+                           const double* seed_gamma, ld_lanes* lanes_out, float* curves_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------
  * Serving: continuous batching of frames from many camera streams.
@@ -354,13 +369,20 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
  * The server owns, per resolution class, up to `inflight` batch engines (a frame object of
  * max_batch frames, device staging for the inputs, its own HIP stream and, if enabled, one
  * captured HIP graph of the whole path at the full batch whose empty slots are masked).
- * Engines are created at ld_server_create as long as their device memory fits hbm_budget;
- * a class that gets no engine does not admit requests (LD_E_NOMEM at submit).
- * ld_server_submit only queues a request (FIFO per class; LD_E_BUSY when max_queue requests
- * wait).  ld_server_poll (non-blocking) collects finished batches and starts new ones: a
- * batch takes queued requests in order, skipping a stream that already has a frame in flight
- * (each stream's frames run in submission order), up to max_batch, as soon as an engine of
- * the class is idle, so requests that arrive while others run join the next free engine.
+ * Admission: an engine is created when its device bytes fit both hbm_budget (with the other
+ * engines) and the device's free memory (hipMemGetInfo, keeping 512 MiB spare): at
+ * ld_server_create round-robin over the classes up to `inflight` per class, and later, at a
+ * poll, for a class whose requests wait with no idle engine; a class that has no engine and no
+ * room takes the place of idle engines of classes with nothing queued.  Requests of a class
+ * without an engine wait in its queue until one is admitted.  ld_server_submit only queues a
+ * request (FIFO per class; LD_E_BUSY when max_queue requests wait; LD_E_NOMEM only for a class
+ * whose single engine exceeds hbm_budget).  ld_server_poll (non-blocking) collects finished
+ * batches and starts new ones: a batch takes queued requests in order, skipping a stream that
+ * already has a frame in flight (each stream's frames run in submission order), up to
+ * max_batch, as soon as an engine of the class is idle, so requests that arrive while others
+ * run join the next free engine.  Input frames are copied on the engine's own stream at the
+ * start of their batch, so they must be complete (and stay alive) by the ld_server_submit call
+ * that hands them over, until their result is returned.
  * Per-stream state stays in device memory: the last V_px fit (seed of the next frame's
  * RANSAC hypothesis 0 when seed_from_state is set) and a frame counter; Philox keys are
  * (seed, stream id) and counters use the stream's frame index, never the batch slot, so a
@@ -381,11 +403,12 @@ typedef struct ld_server_config {
     int32_t inflight;                       /* engines per class, 1..8 */
     int32_t max_queue;                      /* waiting requests per class, >= 1 */
     int32_t use_graphs;                     /* 1: replay a captured graph per engine */
-    int32_t seed_from_state;                /* 1: seed V_px RANSAC with the stream's last fit */
+    int32_t seed_from_state;                /* 1: seed V_px RANSAC with the stream's last fit (also in
+                                               the pruned path, for frames without a seed line) */
     int64_t hbm_budget;                     /* bytes of device memory the engines may use */
     ld_cnn cnn;                             /* nullable: run ld_detect_pruned with this network
-                                               (plain fallback per frame, seed_from_state not
-                                               used); read only, must outlive the server */
+                                               (plain fallback per frame); read only, must
+                                               outlive the server */
 } ld_server_config;
 
 /* One finished request.  Times are host seconds (steady clock) at submit and at the poll

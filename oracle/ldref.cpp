@@ -870,8 +870,8 @@ int ldref_detect(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t 
 
 int ldref_detect_pruned(const uint8_t* grey, int64_t gpitch, const void* disp, int64_t dpitch, int W, int H,
                         int fmt, int d_max, const ldref_params* P, uint64_t stream_id, int64_t frame_idx,
-                        ldref_learned* L, ldref_out* o) {
-    return detect_impl(grey, gpitch, disp, dpitch, W, H, fmt, d_max, P, stream_id, frame_idx, nullptr, o, L);
+                        const double* seed_gamma, ldref_learned* L, ldref_out* o) {
+    return detect_impl(grey, gpitch, disp, dpitch, W, H, fmt, d_max, P, stream_id, frame_idx, seed_gamma, o, L);
 }
 
 }  // extern "C"
@@ -992,8 +992,9 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
     for (int v = v_h; v <= v_max; ++v) { mxv[v - v_h] = v; mxu[v - v_h] = cpath[v] - half; }
 
     // S8: gamma by RANSAC and V_px(v) = g(v) (Eq. vpx_estimation); the narrowed search seeds
-    // hypothesis 0 with the line through the band estimates
-    const double* seed = L ? (((fb & 1) || !L->seed_ransac) ? nullptr : seed_line.data()) : seed_gamma;
+    // hypothesis 0 with the line through the band estimates when it has them (seed_ransac, no
+    // fallback), and otherwise with the caller's seed, as the full search does
+    const double* seed = (L && !(fb & 1) && L->seed_ransac) ? seed_line.data() : seed_gamma;
     ldref_ransac(mxv.data(), mxu.data(), R, 4, P->tr_x, P->n_hyp, P->max_rounds, P->eps_num, P->eps_den,
                  P->seed, stream_id, frame_idx, 1, seed, &o->gamma, o->trace_gamma);
     if (o->gamma.flags & 1) o->flags |= 8;

@@ -104,7 +104,7 @@ def lib():
         L.ldref_detect.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.POINTER(Params), C.c_uint64, C.c_int64, _PD, C.POINTER(Out)]
         L.ldref_detect_pruned.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int,
-                                          C.c_int, C.POINTER(Params), C.c_uint64, C.c_int64, C.POINTER(Learned),
+                                          C.c_int, C.POINTER(Params), C.c_uint64, C.c_int64, _PD, C.POINTER(Learned),
                                           C.POINTER(Out)]
         _lib = L
     return _lib
@@ -351,9 +351,11 @@ class Learned(C.Structure):
 
 def detect_pruned(grey: np.ndarray, disp: np.ndarray, d_max: int, lane_bits: np.ndarray, *, n_bands=1, delta_x=112,
                   dilate=-1, min_votes=8, seed_ransac=0, params: Params | None = None, stream_id=0, frame_idx=0,
-                  want_m1=False):
+                  seed_gamma=None, want_m1=False):
     """The narrowed search given the network's band decisions lane_bits (4 x 16 x W u8):
-    everything detect() reports plus .prune (16 int32) and .cand_mask (2W u8)."""
+    everything detect() reports plus .prune (16 int32) and .cand_mask (2W u8).  seed_gamma
+    (raw-basis quartic, NaN first coefficient: none) is RANSAC hypothesis 0 of V_px whenever the
+    narrowed search itself gives none (seed_ransac off, or a fallback frame)."""
     H, W = np.asarray(grey).shape
     bits = np.ascontiguousarray(lane_bits, dtype=np.uint8).reshape(4, 16, W)
     L = Learned()
@@ -361,7 +363,8 @@ def detect_pruned(grey: np.ndarray, disp: np.ndarray, d_max: int, lane_bits: np.
     L.lane_bits = bits.ctypes.data
     mask = np.zeros(2 * W, np.uint8)
     L.cand_mask = mask.ctypes.data
-    r = detect(grey, disp, d_max, params, stream_id=stream_id, frame_idx=frame_idx, want_m1=want_m1, _learned=L)
+    r = detect(grey, disp, d_max, params, stream_id=stream_id, frame_idx=frame_idx, seed_gamma=seed_gamma,
+               want_m1=want_m1, _learned=L)
     r.prune = np.array(L.prune[:], np.int32)
     r.cand_mask = mask
     return r
@@ -415,7 +418,8 @@ def detect(grey: np.ndarray, disp: np.ndarray, d_max: int, params: Params | None
                            C.byref(params), stream_id, frame_idx, _pd(sg) if sg is not None else None, C.byref(o))
     else:
         lib().ldref_detect_pruned(grey.ctypes.data, grey.strides[0], disp.ctypes.data, disp.strides[0], W, H, fmt,
-                                  d_max, C.byref(params), stream_id, frame_idx, C.byref(_learned), C.byref(o))
+                                  d_max, C.byref(params), stream_id, frame_idx, _pd(sg) if sg is not None else None,
+                                  C.byref(_learned), C.byref(o))
     r.flags, r.v_h, r.v_end, r.n_lanes = o.flags, o.v_h, o.v_end, o.n_lanes
     r.n_my, r.n_edges, r.n_votes = o.n_my, o.n_edges, o.n_votes
     r.my_x = r.my_x[: o.n_my]

@@ -1257,8 +1257,8 @@ __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(7))) void 
 
 // S8 for every frame: RANSAC of the quartic through the row-DP path (read back from the path
 // columns), V_px and the track tables.  One 128-thread workgroup per frame (the RANSAC's
-// registers allow many per CU).  Hypothesis 0: the caller's seed rows (plain search), or the
-// seed of the narrowed search for the frames that kept it (pruned = 1).
+// registers allow many per CU).  Hypothesis 0: the seed of the narrowed search for the frames
+// that kept one (pruned = 1), otherwise the caller's seed rows.
 // Three waves per frame: the inlier counts of a round split the points over the waves, and
 // three 192-thread workgroups per CU still hold every frame of a 1024 batch at once.
 #ifndef LD_RANSAC_THREADS
@@ -1299,12 +1299,11 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
         PY[v - v_h] = d.mxpath[(int64_t)b * H + v] - d.half;
     }
     __syncthreads();
-    const double* seed = nullptr;
-    if (pruned) {
-        if (!(d.prune[(int64_t)b * kPruneWords + 1] & kFbPlainVpx)) seed = d.seedg + 5 * (int64_t)b;
-    } else if (seed_gamma) {
-        seed = seed_gamma + 5 * (int64_t)b;
-    }
+    // hypothesis 0: the narrowed search's own seed when it has one (no fallback, a seed line
+    // drawn), else the caller's seed (NaN first coefficient or NULL: none)
+    const double* seed = seed_gamma ? seed_gamma + 5 * (int64_t)b : nullptr;
+    if (pruned && !(d.prune[(int64_t)b * kPruneWords + 1] & kFbPlainVpx) && !isnan(d.seedg[5 * (int64_t)b]))
+        seed = d.seedg + 5 * (int64_t)b;
     vpx_fit_tail(d, b, fi, PX, PY, cur, cur2, bitmap, bm_words, S, stream_ids, frame_idx, seed, vp_out);
 }
 
@@ -2681,8 +2680,9 @@ ld_status ld_detect_noalloc(int32_t width, int32_t height, int32_t batch, int32_
 
 ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                            int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
-                           ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+                           const double* seed_gamma, ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
     if (!f || !n || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
+    if (seed_gamma && !aligned(seed_gamma, 8)) return LD_E_INVAL;
     if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
     if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
     if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
@@ -2726,7 +2726,7 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     full.only_bits = kFbPlainVpx;
     full.only_set = 1;
     if (s == LD_OK) s = run_vpx_dp(f, full, st);
-    if (s == LD_OK) s = run_vpx_ransac(f, stream_ids, frame_idx, nullptr, 1, nullptr, st);
+    if (s == LD_OK) s = run_vpx_ransac(f, stream_ids, frame_idx, seed_gamma, 1, nullptr, st);
     if (s == LD_OK) {
         ProfScope ps(f, 9, st);
         const size_t lm = sizeof(uint32_t) * nb * LDI_BAND_ROWS * (size_t)((d.W + 31) / 32) + (size_t)d.W2;

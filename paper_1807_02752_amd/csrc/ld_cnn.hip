@@ -21,8 +21,12 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "ld.h"
 #include "ld_internal.h"
@@ -973,6 +977,101 @@ ld_status ld_cnn_get_params(ld_cnn n, float* params) {
     if (!n || !params) return LD_E_INVAL;
     if (hipStreamSynchronize(n->last) != hipSuccess) return LD_E_HIP;
     return hip_ok(hipMemcpy(params, n->master, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+}
+
+// Checkpoint file: one header line of JSON, then the FP32 master weights, the Adam first and
+// second moments (kNP little-endian float32 each, in that order).
+namespace {
+
+constexpr const char* kCkptFormat = "ld_cnn_checkpoint";
+constexpr int kCkptVersion = 1;
+
+std::string ckpt_header(const ld_cnn_s& n) {
+    char buf[512];
+    const ld_cnn_config& c = n.cfg;
+    snprintf(buf, sizeof(buf),
+             "{\"format\": \"%s\", \"version\": %d, \"params\": %d, \"step\": %lld, \"dtype\": \"float32\", "
+             "\"arrays\": [\"master\", \"adam_m\", \"adam_v\"], \"config\": {\"n_bands\": %d, \"theta\": %.9g, "
+             "\"delta_x\": %d, \"dilate\": %d, \"min_votes\": %d, \"max_batch\": %d, \"max_width\": %d, "
+             "\"seed_ransac\": %d}}\n",
+             kCkptFormat, kCkptVersion, kNP, (long long)n.step, c.n_bands, (double)c.theta, c.delta_x, c.dilate,
+             c.min_votes, c.max_batch, c.max_width, c.seed_ransac);
+    return buf;
+}
+
+// the number after "key": in a header line (false if absent)
+bool ckpt_number(const std::string& h, const char* key, double& out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t p = h.find(k);
+    if (p == std::string::npos) return false;
+    const char* s = h.c_str() + p + k.size();
+    char* end = nullptr;
+    out = strtod(s, &end);
+    return end != s;
+}
+
+}  // namespace
+
+ld_status ld_cnn_save(ld_cnn n, const char* path) {
+    if (!n || !path) return LD_E_INVAL;
+    if (hipStreamSynchronize(n->last) != hipSuccess) return LD_E_HIP;
+    std::vector<float> buf((size_t)3 * kNP);
+    if (hipMemcpy(buf.data(), n->master, sizeof(float) * kNP, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + kNP, n->am, sizeof(float) * kNP, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(buf.data() + 2 * kNP, n->av, sizeof(float) * kNP, hipMemcpyDeviceToHost) != hipSuccess)
+        return LD_E_HIP;
+    const std::string h = ckpt_header(*n);
+    FILE* fp = fopen(path, "wb");
+    if (!fp) return LD_E_INVAL;
+    const bool ok = fwrite(h.data(), 1, h.size(), fp) == h.size() &&
+                    fwrite(buf.data(), sizeof(float), buf.size(), fp) == buf.size();
+    const bool closed = fclose(fp) == 0;
+    return ok && closed ? LD_OK : LD_E_INVAL;
+}
+
+ld_status ld_cnn_load(const char* path, const ld_cnn_config* cfg, ld_cnn* out) {
+    if (!path || !out) return LD_E_INVAL;
+    *out = nullptr;
+    FILE* fp = fopen(path, "rb");
+    if (!fp) return LD_E_INVAL;
+    std::string h;
+    int ch;
+    while ((ch = fgetc(fp)) != EOF && ch != '\n' && h.size() < 4096) h.push_back((char)ch);
+    std::vector<float> buf((size_t)3 * kNP);
+    const bool got = ch == '\n' && fread(buf.data(), sizeof(float), buf.size(), fp) == buf.size() && fgetc(fp) == EOF;
+    fclose(fp);
+    double version = 0, params = 0, step = -1;
+    if (!got || h.find(std::string("\"format\": \"") + kCkptFormat + "\"") == std::string::npos ||
+        !ckpt_number(h, "version", version) || version != kCkptVersion || !ckpt_number(h, "params", params) ||
+        params != kNP || !ckpt_number(h, "step", step) || step < 0 || step != std::floor(step))
+        return LD_E_INVAL;
+    ld_cnn_config c;
+    if (cfg) {
+        c = *cfg;
+    } else {
+        ld_cnn_config_default(&c);
+        double x;
+        if (ckpt_number(h, "n_bands", x)) c.n_bands = (int32_t)x;
+        if (ckpt_number(h, "theta", x)) c.theta = (float)x;
+        if (ckpt_number(h, "delta_x", x)) c.delta_x = (int32_t)x;
+        if (ckpt_number(h, "dilate", x)) c.dilate = (int32_t)x;
+        if (ckpt_number(h, "min_votes", x)) c.min_votes = (int32_t)x;
+        if (ckpt_number(h, "max_batch", x)) c.max_batch = (int32_t)x;
+        if (ckpt_number(h, "max_width", x)) c.max_width = (int32_t)x;
+        if (ckpt_number(h, "seed_ransac", x)) c.seed_ransac = (int32_t)x;
+    }
+    if (!valid_config(c)) return LD_E_INVAL;
+    ld_cnn n = nullptr;
+    ld_status s = ld_cnn_create(&c, buf.data(), &n);
+    if (s != LD_OK) return s;
+    if (hipMemcpy(n->am, buf.data() + kNP, sizeof(float) * kNP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(n->av, buf.data() + 2 * kNP, sizeof(float) * kNP, hipMemcpyHostToDevice) != hipSuccess) {
+        ld_cnn_destroy(n);
+        return LD_E_HIP;
+    }
+    n->step = (int64_t)step;
+    *out = n;
+    return LD_OK;
 }
 
 ld_status ld_cnn_forward(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,

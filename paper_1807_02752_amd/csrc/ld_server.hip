@@ -102,6 +102,8 @@ struct ld_server_s {
     int64_t next_req = 0;
     int64_t bytes = 0;
     int32_t per_class[LD_MAX_CLASSES] = {0, 0, 0, 0};
+    int64_t admitted = 0;    // engines created after ld_server_create
+    int64_t evicted = 0;     // idle engines freed to admit another class
 };
 
 namespace {
@@ -111,6 +113,21 @@ size_t engine_bytes(const ld_server_config& c, int k) {
     const size_t staging = B * H * W * (1 + (size_t)elem_size(c.fmt[k]));
     const size_t small = B * (8 + 8 + 5 * 8 + sizeof(ld_lanes)) + 64;
     return ldi_frame_bytes(c.width[k], c.height[k], c.max_batch[k], c.d_max[k]) + staging + small + 4096;
+}
+
+// Device memory kept free beyond an engine's own bytes when an engine is admitted.
+constexpr int64_t kReserveBytes = (int64_t)512 << 20;
+
+// An engine of class k fits the caller's budget and the device's free memory now.
+bool can_admit(ld_server s, int k) {
+    const int64_t need = (int64_t)engine_bytes(s->cfg, k);
+    if (s->bytes + need > s->cfg.hbm_budget) return false;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return (int64_t)free_b >= need + kReserveBytes;
 }
 
 void free_engine(Engine* e) {
@@ -141,14 +158,14 @@ ld_status enqueue_batch_body(ld_server s, Engine* e) {
     const int B = e->B;
     const int64_t gp = e->W, dpt = (int64_t)e->W * e->es;
     ld_status r = LD_OK;
+    const bool seed = s->cfg.seed_from_state != 0;
+    if (seed)
+        hipLaunchKernelGGL(k_gather_seeds, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact,
+                           e->d_seed);
     if (s->cfg.cnn) {
-        r = ld_detect_pruned(e->f, s->cfg.cnn, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx, e->d_lanes, nullptr,
-                             e->st);
+        r = ld_detect_pruned(e->f, s->cfg.cnn, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx,
+                             seed ? e->d_seed : nullptr, e->d_lanes, nullptr, e->st);
     } else {
-        const bool seed = s->cfg.seed_from_state != 0;
-        if (seed)
-            hipLaunchKernelGGL(k_gather_seeds, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact,
-                               e->d_seed);
         r = ld_vdisp(e->f, e->d_disp, dpt, e->d_sid, e->d_fidx, nullptr, nullptr, e->st);
         if (r == LD_OK)
             r = ld_vp_ransac(e->f, e->d_grey, gp, e->d_disp, dpt, e->d_sid, e->d_fidx, seed ? e->d_seed : nullptr, nullptr,
@@ -281,7 +298,7 @@ ld_status ld_server_create(const ld_server_config* cfg, const ld_params* p, ld_s
         grew = false;
         for (int k = 0; k < c.n_classes; ++k) {
             const int64_t need = (int64_t)engine_bytes(c, k);
-            if (s->bytes + need > c.hbm_budget) continue;
+            if (!can_admit(s, k)) continue;
             Engine* e = nullptr;
             const ld_status st = make_engine(s, k, &e);
             if (st == LD_E_NOMEM) continue;
@@ -311,7 +328,7 @@ ld_status ld_server_submit(ld_server s, int32_t stream_id, int32_t cls, const ui
     const int W = s->cfg.width[cls], es = elem_size(s->cfg.fmt[cls]);
     if (grey_pitch < W || disp_pitch < (int64_t)W * es) return LD_E_INVAL;
     if (s->stream_cls[stream_id] >= 0 && s->stream_cls[stream_id] != cls) return LD_E_INVAL;   // a stream keeps its size
-    if (s->per_class[cls] == 0) return LD_E_NOMEM;                                           // class not admitted
+    if ((int64_t)engine_bytes(s->cfg, cls) > s->cfg.hbm_budget) return LD_E_NOMEM;          // never admissible
     if ((int)s->queue[cls].size() >= s->cfg.max_queue) return LD_E_BUSY;
     s->stream_cls[stream_id] = cls;
     Request r;
@@ -358,8 +375,41 @@ ld_status ld_server_poll(ld_server s, ld_server_result* results, int32_t max_res
     // 2. start batches on idle engines
     for (Engine* e : s->engines)
         if (!e->busy && !s->queue[e->cls].empty()) start_batch(s, e);
+    // 3. admission: a class with waiting requests and no idle engine gets a new engine when its
+    // bytes fit the budget and the free device memory; a class with no engine at all may take the
+    // place of idle engines of classes that have nothing queued
+    for (int k = 0; k < s->cfg.n_classes; ++k) {
+        if (s->queue[k].empty()) continue;
+        bool idle = false;
+        for (Engine* e : s->engines) idle = idle || (e->cls == k && !e->busy);
+        if (idle || s->per_class[k] >= s->cfg.inflight) continue;
+        if (s->per_class[k] == 0) {
+            for (size_t i = 0; i < s->engines.size() && !can_admit(s, k);) {
+                Engine* e = s->engines[i];
+                if (!e->busy && e->cls != k && s->queue[e->cls].empty()) {
+                    s->bytes -= (int64_t)engine_bytes(s->cfg, e->cls);
+                    s->per_class[e->cls] -= 1;
+                    free_engine(e);
+                    s->engines.erase(s->engines.begin() + (ptrdiff_t)i);
+                    s->evicted += 1;
+                } else {
+                    ++i;
+                }
+            }
+        }
+        if (!can_admit(s, k)) continue;
+        Engine* e = nullptr;
+        const ld_status st = make_engine(s, k, &e);
+        if (st == LD_E_NOMEM) continue;
+        if (st != LD_OK) { status = st; continue; }
+        s->engines.push_back(e);
+        s->bytes += (int64_t)engine_bytes(s->cfg, k);
+        s->per_class[k] += 1;
+        s->admitted += 1;
+        start_batch(s, e);
+    }
     if (hipGetLastError() != hipSuccess) status = LD_E_HIP;
-    // 3. hand out results
+    // 4. hand out results
     int n = 0;
     while (n < max_results && !s->finished.empty()) {
         results[n++] = s->finished.front();

@@ -126,7 +126,11 @@ def lib():
         L.ld_cnn_forward.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp]
         L.ld_cnn_labels.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp, vp]
         L.ld_cnn_train_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp]
-        L.ld_detect_pruned.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.ld_detect_pruned.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.ld_cnn_save.argtypes = [vp, C.c_char_p]
+        L.ld_cnn_load.argtypes = [C.c_char_p, C.POINTER(ld_cnn_config), C.POINTER(vp)]
+        L.ld_cnn_save.restype = i32
+        L.ld_cnn_load.restype = i32
         L.ld_detect_noalloc.argtypes = [i32, i32, i32, i32, i32, C.POINTER(ld_params), vp, i64, vp, i64, vp, vp,
                                         vp, vp, vp]
         L.ld_detect_noalloc.restype = i32
@@ -146,7 +150,8 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_frame_read", "ld_frame_profile", "ld_frame_kernel_times", "ld_server_create", "ld_server_destroy",
             "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
-            "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc"]
+            "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc",
+            "ld_cnn_save", "ld_cnn_load"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -308,9 +313,35 @@ def ld_cnn_train_step(n, f, grey, grey_pitch, disp, disp_pitch, labels, pos_weig
                                    loss_out, grad_out, stream)
 
 
-def ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out, curves_out, stream):
-    return lib().ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, lanes_out,
-                                  curves_out, stream)
+def ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, seed_gamma, lanes_out,
+                     curves_out, stream):
+    return lib().ld_detect_pruned(f, n, grey, grey_pitch, disp, disp_pitch, stream_ids, frame_idx, seed_gamma,
+                                  lanes_out, curves_out, stream)
+
+
+def ld_cnn_save(n, path):
+    return lib().ld_cnn_save(n, os.fsencode(path))
+
+
+def ld_cnn_load(path, cfg=None):
+    h = C.c_void_p()
+    st = lib().ld_cnn_load(os.fsencode(path), C.byref(cfg) if cfg is not None else None, C.byref(h))
+    return st, h
+
+
+CKPT_FIELDS = ("master", "adam_m", "adam_v")
+
+
+def read_checkpoint(path):
+    """(header dict, {array name: float32 array}) of a file written by ld_cnn_save."""
+    import json
+    with open(path, "rb") as fp:
+        header = json.loads(fp.readline().decode())
+        data = np.frombuffer(fp.read(), dtype="<f4")
+    n = header["params"]
+    if data.size != len(CKPT_FIELDS) * n:
+        raise LdError(f"checkpoint {path}: {data.size} floats, expected {len(CKPT_FIELDS) * n}")
+    return header, {k: data[i * n:(i + 1) * n].copy() for i, k in enumerate(CKPT_FIELDS)}
 
 
 def cnn_config(**overrides) -> ld_cnn_config:
@@ -472,9 +503,11 @@ class Detector:
     def parse_lanes(buf) -> np.ndarray:
         return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=LANES_DTYPE)
 
-    def detect_pruned(self, net: "Cnn", grey, disp, lanes_out, stream_ids=None, frame_idx=None, curves_out=None):
+    def detect_pruned(self, net: "Cnn", grey, disp, lanes_out, stream_ids=None, frame_idx=None, curves_out=None,
+                      seed_gamma=None):
         check(ld_detect_pruned(self.handle, net.handle, _ptr(grey), self._pitch(grey), _ptr(disp), self._pitch(disp),
-                               _ptr(stream_ids), _ptr(frame_idx), _ptr(lanes_out), _ptr(curves_out), _stream()),
+                               _ptr(stream_ids), _ptr(frame_idx), _ptr(seed_gamma), _ptr(lanes_out),
+                               _ptr(curves_out), _stream()),
               "ld_detect_pruned")
 
     def read(self, what: int, b: int = 0) -> np.ndarray:
@@ -522,6 +555,23 @@ class Cnn:
             self.close()
         except Exception:
             pass
+
+    def save(self, path):
+        """Checkpoint: master weights, Adam moments and step (ld_cnn_save)."""
+        check(ld_cnn_save(self.handle, path), "ld_cnn_save")
+
+    @classmethod
+    def load(cls, path, **config):
+        """A network restored from a checkpoint (its own configuration unless config is given)."""
+        obj = cls.__new__(cls)
+        obj.config = cnn_config(**config) if config else None
+        st, h = ld_cnn_load(path, obj.config)
+        check(st, "ld_cnn_load")
+        obj.handle = h
+        if obj.config is None:
+            header, _ = read_checkpoint(path)
+            obj.config = cnn_config(**header["config"])
+        return obj
 
     def set_params(self, params):
         arr = np.ascontiguousarray(params, dtype=np.float32)

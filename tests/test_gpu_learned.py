@@ -193,6 +193,48 @@ def test_training_step_is_deterministic():
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_checkpoint_resume_continues_training_exactly(tmp_path):
+    """ld_cnn_save after three Adam steps, then a fourth step; a network restored by
+    ld_cnn_load takes the same fourth step: the weights match bit for bit (and they would not
+    if the moments or the step count were lost: the restored step differs from a fresh one)."""
+    ld = _ld()
+    greys, disps = frames_c2(2, seed=6)
+    B, H, W = greys.shape
+    params = random_params(5)
+    labels = torch.from_numpy(_labels_for(np.random.default_rng(3), B, 2, W)).cuda()
+    g, d = torch.from_numpy(greys).cuda(), torch.from_numpy(disps).cuda()
+    det = ld.Detector(W, H, B, ld.LD_DISP_F32, 128)
+    det.vdisp(d)
+    net = ld.Cnn(params, n_bands=2, max_batch=B, max_width=W, theta=0.4)
+    for _ in range(3):
+        net.train_step(det, g, d, labels, 4.0, 1e-5, 1e-3)
+    path = str(tmp_path / "net.ckpt")
+    net.save(path)
+    saved = net.get_params()
+    header, arrays = ld.read_checkpoint(path)
+    assert header["step"] == 3 and header["params"] == ld.LD_CNN_PARAMS
+    assert abs(header["config"]["theta"] - 0.4) < 1e-7 and header["config"]["n_bands"] == 2
+    assert np.array_equal(arrays["master"], saved)
+    assert np.abs(arrays["adam_v"]).max() > 0
+    net.train_step(det, g, d, labels, 4.0, 1e-5, 1e-3)
+    det.sync()
+    cont = net.get_params()
+    net.close()
+    back = ld.Cnn.load(path)
+    assert back.config.n_bands == 2 and abs(back.config.theta - 0.4) < 1e-7
+    assert np.array_equal(back.get_params(), saved)
+    back.train_step(det, g, d, labels, 4.0, 1e-5, 1e-3)
+    det.sync()
+    assert np.array_equal(back.get_params(), cont)
+    back.close()
+    fresh = ld.Cnn(saved, n_bands=2, max_batch=B, max_width=W)   # same weights, no moments, step 0
+    fresh.train_step(det, g, d, labels, 4.0, 1e-5, 1e-3)
+    det.sync()
+    assert not np.array_equal(fresh.get_params(), cont)
+    fresh.close()
+    det.close()
+
+
 def test_labels_from_plain_curves():
     ld = _ld()
     greys, disps = frames_c2(3, seed=1)

@@ -15,7 +15,7 @@ from paper_1807_02752_amd import synth
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-CLASSES = [(320, 96, 0, 48, 4), (640, 192, 0, 96, 3)]
+CLASSES = [(320, 96, 0, 48, 4), (640, 192, 0, 96, 3), (1920, 1080, 0, 255, 2)]
 
 
 def _ld():
@@ -73,9 +73,10 @@ def _bright_net():
 
 
 def _pruned_alone(frames, s, net):
-    """One stream alone, frame by frame, through ld_detect_pruned with the stream's ids."""
+    """One stream alone, frame by frame, through ld_detect_pruned with the stream's ids and its
+    previous V_px fit as seed (NaN: none)."""
     ld = _ld()
-    res = []
+    res, seed = [], np.full(5, np.nan)
     for k, (g, d, cls) in enumerate(frames):
         W, H, fmt, dm, _ = CLASSES[cls]
         det = ld.Detector(W, H, 1, fmt, dm)
@@ -83,10 +84,14 @@ def _pruned_alone(frames, s, net):
         dt = torch.from_numpy(d[None]).cuda()
         sid = torch.tensor([s], dtype=torch.int64).cuda()
         fid = torch.tensor([k], dtype=torch.int64).cuda()
+        sg = torch.from_numpy(seed[None].copy()).cuda()
         lanes = det.lanes_buffer()
-        det.detect_pruned(net, gt, dt, lanes, stream_ids=sid, frame_idx=fid)
+        det.detect_pruned(net, gt, dt, lanes, stream_ids=sid, frame_idx=fid, seed_gamma=sg)
         det.sync()
         L = ld.Detector.parse_lanes(lanes)[0]
+        gam = det.read(ld.LD_STATE_GAMMA, 0)[0]
+        if gam["ok"]:
+            seed = np.array(gam["raw"], dtype=np.float64)
         res.append((int(L["n"]), int(L["flags"]), list(L["u_start"][: L["n"]]), list(L["energy"][: L["n"]])))
         det.close()
     return res
@@ -137,8 +142,9 @@ def test_server_equals_each_frame_alone(use_graphs):
 
 @pytest.mark.parametrize("use_graphs", [True, False])
 def test_server_pruned_equals_each_frame_alone(use_graphs):
-    """With a network the server runs the pruned path; each frame's lanes (and fallback flags)
-    equal those of the frame run alone through ld_detect_pruned."""
+    """With a network the server runs the pruned path, its V_px RANSAC seeded from the stream's
+    state; each frame's lanes (and fallback flags) equal those of the frame run alone through
+    ld_detect_pruned in stream order with the stream's previous fit as seed."""
     frames = _frames(5, 4)
     rng = np.random.default_rng(2)
     order = [s for s in frames for _ in range(len(frames[s]))]
@@ -170,31 +176,47 @@ def test_sequential_seeded_chain_matches_oracle():
 
 
 def test_server_admission_by_budget_and_queue():
+    """Engines fit the byte budget together: a class whose engine does not fit beside the others
+    waits in its queue and is admitted in the place of an idle engine of a class with nothing
+    queued; a class whose single engine exceeds the budget is refused; the queue is bounded."""
     ld = _ld()
-    W, H, fmt, dm, mb = CLASSES[0]
-    W2, H2, fmt2, dm2, mb2 = CLASSES[1]
-    probe = ld.Server(ld.server_config([CLASSES[0]], n_streams=4, inflight=1, use_graphs=False))
-    _, one = probe.engines()
-    probe.close()
-    # budget for one small-class engine only: the large class admits nothing
-    cfg = ld.server_config([CLASSES[0], CLASSES[1]], n_streams=4, inflight=2, max_queue=2, use_graphs=False,
-                           hbm_budget=one + 1024)
+    small, large = CLASSES[0], CLASSES[1]
+    sizes = []
+    for c in (small, large):
+        probe = ld.Server(ld.server_config([c], n_streams=4, inflight=1, use_graphs=False))
+        sizes.append(probe.engines()[1])
+        probe.close()
+    budget = max(sizes) + 1024                    # room for either engine, not for both
+    assert sum(sizes) > budget
+    cfg = ld.server_config([small, large], n_streams=4, inflight=1, max_queue=2, use_graphs=False, hbm_budget=budget)
     srv = ld.Server(cfg)
     per_class, used = srv.engines()
-    assert per_class[:2] == [1, 0] and used <= one + 1024
-    g, d = synth.make_scaled_c1(W, H, dm, seed=5, idx=0)[:2]
-    gt, dt = torch.from_numpy(g).cuda(), torch.from_numpy(d).cuda()
-    g2, d2 = synth.make_scaled_c1(W2, H2, dm2, seed=5, idx=0)[:2]
-    gt2, dt2 = torch.from_numpy(g2).cuda(), torch.from_numpy(d2).cuda()
-    assert srv.submit(1, 1, gt2, dt2)[0] == ld.LD_E_NOMEM
-    assert srv.submit(0, 0, gt, dt)[0] == ld.LD_OK
-    assert srv.submit(0, 0, gt, dt)[0] == ld.LD_OK
-    assert srv.submit(2, 0, gt, dt)[0] == ld.LD_E_BUSY           # max_queue = 2
-    done = []
-    for _ in range(100000):
-        done += srv.poll()
-        if len(done) == 2:
-            break
+    assert per_class[:2] == [1, 0] and used <= budget
+    frames = []
+    for c in (small, large):
+        g, d = synth.make_scaled_c1(c[0], c[1], c[3], seed=5, idx=0)[:2]
+        frames.append((torch.from_numpy(g).cuda(), torch.from_numpy(d).cuda()))
+
+    def drain(n):
+        done = []
+        for _ in range(200000):
+            done += srv.poll()
+            if len(done) >= n:
+                break
+        return done
+
+    assert srv.submit(1, 1, *frames[1])[0] == ld.LD_OK          # queued: no engine of its class yet
+    done = drain(1)
+    assert [(r["stream"], r["cls"]) for r in done] == [(1, 1)]
+    assert srv.engines()[0][:2] == [0, 1]                        # the idle small engine gave way
+    assert srv.submit(0, 0, *frames[0])[0] == ld.LD_OK
+    assert srv.submit(0, 0, *frames[0])[0] == ld.LD_OK
+    assert srv.submit(2, 0, *frames[0])[0] == ld.LD_E_BUSY       # max_queue = 2
+    done = drain(2)
     assert [r["frame_idx"] for r in done] == [0, 1]               # one stream: in order, one at a time
-    assert srv.submit(2, 0, gt, dt)[0] == ld.LD_OK
+    assert srv.engines()[0][:2] == [1, 0]
     srv.close()
+    tiny = ld.Server(ld.server_config([small, large], n_streams=2, inflight=1, use_graphs=False,
+                                      hbm_budget=min(sizes) + 1024))
+    assert tiny.submit(0, 1, *frames[1])[0] == ld.LD_E_NOMEM     # its engine can never fit
+    tiny.close()

@@ -321,6 +321,30 @@ def test_ideal_decisions_return_the_plain_lanes(seq, idx):
                 assert r.prune[14] < 2 * W
 
 
+def test_caller_seed_in_the_narrowed_search():
+    """A caller's RANSAC seed (a stream's previous fit) is hypothesis 0 of the narrowed search
+    as of the full one: with ideal decisions (same DP path) the V_px fit, its trace and the lanes
+    equal those of the full search with that seed; a fallback frame (no marked edge) uses it too;
+    a NaN seed is no seed."""
+    g, d, _ = synth.make_batch("c2", 9, 2, 20)
+    H, W = g.shape[1:]
+    P = oracle.default_params(n_hyp=1)                    # one hypothesis per round: the seed's, when given
+    prev = oracle.detect(g[0], d[0], 128, P, frame_idx=20)
+    seed = np.array(prev.gamma.raw[:5])
+    plain = oracle.detect(g[1], d[1], 128, P, frame_idx=21, seed_gamma=seed)
+    unseeded = oracle.detect(g[1], d[1], 128, P, frame_idx=21)
+    assert plain.trace_gamma.tolist() != unseeded.trace_gamma.tolist()
+    bits = _plain_curve_bits(oracle.detect(g[1], d[1], 128, frame_idx=21), H, W, 1)   # the lanes, marked
+    r = oracle.detect_pruned(g[1], d[1], 128, bits, params=P, frame_idx=21, seed_gamma=seed)
+    assert r.prune[1] == 0 and np.array_equal(r.mx_path, plain.mx_path)
+    assert r.trace_gamma.tolist() == plain.trace_gamma.tolist() and list(r.gamma.raw) == list(plain.gamma.raw)
+    assert r.u_start.tolist() == plain.u_start.tolist()
+    fb = oracle.detect_pruned(g[1], d[1], 128, np.zeros((4, 16, W), np.uint8), params=P, frame_idx=21, seed_gamma=seed)
+    assert fb.prune[1] & 1 and fb.trace_gamma.tolist() == plain.trace_gamma.tolist()
+    none = oracle.detect_pruned(g[1], d[1], 128, bits, params=P, frame_idx=21, seed_gamma=np.full(5, np.nan))
+    assert none.trace_gamma.tolist() == unseeded.trace_gamma.tolist()
+
+
 def test_narrowed_search_fallbacks():
     """No marked edge: no seed, the full search, the plain lanes, flag FALLBACK.  A window of
     one column (delta 0) pinned on the seed must reach its inner edge and fall back."""
