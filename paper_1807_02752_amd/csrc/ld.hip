@@ -1750,22 +1750,17 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     const int H = d.H, W2 = d.W2, v_max = H - 1;
     FrameInfo fi = d.info[b];
     for (int v = l; v < H; v += kWave) d.mxpath[(int64_t)b * H + v] = -1;
-    // per-frame values are wave-uniform: kept in scalar registers, so the row loop's tests on
-    // them are scalar branches
-    const int v_h = __builtin_amdgcn_readfirstlane(fi.v_h), chi = d.P.chi, R = v_max - v_h + 1;
-    const int lo = __builtin_amdgcn_readfirstlane(pr[3]), hi = __builtin_amdgcn_readfirstlane(pr[4]);
-    const int win = hi - lo + 1;
-    int* dlt0 = reinterpret_cast<int*>(smem);                // 2 x 256 band deltas, by row parity
-    int* sink = dlt0 + 512;                                   // 64: one per lane, for atomics without a key
-    int* cntL = sink + kWave;                                 // H
+    const int v_h = fi.v_h, chi = d.P.chi, R = v_max - v_h + 1;
+    const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
+    int* dlt = reinterpret_cast<int*>(smem);                 // 256 band deltas of a row
+    int* cntL = dlt + 256;                                    // H
     int* path = cntL + H;                                     // H + 1 (the last: touch flag)
     int* roff = path + H + 1;                                 // R + 1 <= H + 1
     uint8_t* wb = reinterpret_cast<uint8_t*>(roff + H + 1);               // stage_cap bytes
     uint16_t* back = reinterpret_cast<uint16_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 2;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
     for (int v = l; v < H; v += kWave) cntL[v] = d.rowcnt[(int64_t)b * H + v];
-    for (int i = l; i < 512; i += kWave) dlt0[i] = 0;
-    auto dlt = [&](int v) -> int* { return dlt0 + 256 * (v & 1); };
+    for (int i = l; i < 256; i += kWave) dlt[i] = 0;
     {   // exclusive prefix of the road rows' edge counts, 64 rows per wave scan
         int carry = 0;
         for (int base = 0; base < R; base += kWave) {
@@ -1834,8 +1829,8 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         for (int v = v_h; v <= v_max; ++v)
             for (int i = l; i < cntL[v]; i += kWave) nv += fe[(int64_t)v * d.W + i].bin >= 0 ? 1 : 0;
     }
-    // band rows entering (sign +1) or leaving (-1) the accumulator, into the deltas dd
-    auto apply = [&](int r, int sign, int* dd) {
+    // band rows entering (sign +1) or leaving (-1) the accumulator
+    auto apply = [&](int r, int sign) {
         const int n = cntL[r];
         const int o = staged ? roff[r - v_h] : 0;
         for (int base = 0; base < n; base += kWave) {
@@ -1850,19 +1845,19 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
                     key = (c >= lo && c <= hi) ? c - lo : -1;
                 }
             }
-            if (key >= 0) atomicAdd(&dd[key], sign);
+            if (key >= 0) atomicAdd(&dlt[key], sign);
         }
     };
-    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1, dlt(v_max));
+    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1);
     // S = 16 E of the own columns (kBig outside the window).  A candidate from column c + tau
     // costs S(c + tau) + slope |tau| - [tau < 0] with slope = 16 lambda + 2, i.e. 16 (E + lambda
     // |tau|) plus the rank of tau in the tie order 0, -1, +1, -2, +2, ..., so one min picks the
     // cost and the tie; offsets are taken relative to the lane's first column 4l.
     int h[4], S[4];
     {
-        const int4 q = *reinterpret_cast<const int4*>(dlt(v_max) + 4 * l);
+        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
         h[0] = q.x; h[1] = q.y; h[2] = q.z; h[3] = q.w;
-        *reinterpret_cast<int4*>(dlt(v_max) + 4 * l) = make_int4(0, 0, 0, 0);
+        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) S[j] = 4 * l + j < win ? -16 * h[j] : kBig;
@@ -1882,10 +1877,10 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         nR = (r >= v_h && rr <= v_max) ? cntL[min(rr, v_max)] : 0;
         oR = roff[min(max(rr - v_h, 0), R)];
     };
-    // read unconditionally (the staged offsets are in range whenever a lane has an entry)
     auto own_key = [&](int n, int o) -> int {
-        const int c = wb[min(o + l, stage_cap - 1)];
-        return (l < n && c != 255) ? c : -1;
+        if (l >= n) return -1;
+        const int c = wb[o + l];
+        return c != 255 ? c : -1;
     };
     if (staged) {
         heads(v_max - 1, nA1, oA1, nR1, oR1);
@@ -1893,14 +1888,10 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         kA = own_key(nA1, oA1);
         kR = own_key(nR1, oR1);
     }
-    // the band changes of row v (votes of row v - chi entering, of row v + chi + 1 leaving) go
-    // into the deltas of v's parity one row early, so their LDS atomics run while the row
-    // before is computed; a row then reads its finished deltas first
-    auto changes = [&](int v, int* dd) {
+    for (int v = v_max - 1; v >= v_h; --v) {
         if (staged) {
-            // every lane adds; a lane without an entry adds 0 to its own sink word
-            atomicAdd(kA >= 0 ? &dd[kA] : &sink[l], kA >= 0 ? 1 : 0);
-            atomicAdd(kR >= 0 ? &dd[kR] : &sink[l], kR >= 0 ? -1 : 0);
+            if (kA >= 0) atomicAdd(&dlt[kA], 1);
+            if (kR >= 0) atomicAdd(&dlt[kR], -1);
             // long lists: four offsets read before their atomics
             for (int i0 = l + kWave; i0 < max(nA1, nR1); i0 += 2 * kWave) {
                 int ca[2], cr[2];
@@ -1912,8 +1903,8 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
                 }
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    if (ca[j] != 255) atomicAdd(&dd[ca[j]], 1);
-                    if (cr[j] != 255) atomicAdd(&dd[cr[j]], -1);
+                    if (ca[j] != 255) atomicAdd(&dlt[ca[j]], 1);
+                    if (cr[j] != 255) atomicAdd(&dlt[cr[j]], -1);
                 }
             }
             kA = own_key(nA2, oA2);                 // row v - 1
@@ -1921,17 +1912,13 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
             nA1 = nA2; oA1 = oA2; nR1 = nR2; oR1 = oR2;
             heads(v - 2, nA2, oA2, nR2, oR2);
         } else {
-            if (v - chi >= v_h) apply(v - chi, 1, dd);
-            if (v + chi + 1 <= v_max) apply(v + chi + 1, -1, dd);
+            if (v - chi >= v_h) apply(v - chi, 1);
+            if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
         }
-    };
-    if (v_max - 1 >= v_h) changes(v_max - 1, dlt(v_max - 1));
-    for (int v = v_max - 1; v >= v_h; --v) {
-        // the wave's LDS operations complete in order: the deltas of row v are final here
-        const int4 q = *reinterpret_cast<const int4*>(dlt(v) + 4 * l);
-        *reinterpret_cast<int4*>(dlt(v) + 4 * l) = make_int4(0, 0, 0, 0);
+        // the wave's LDS operations complete in order: the deltas are final here
+        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
+        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
         h[0] += q.x; h[1] += q.y; h[2] += q.z; h[3] += q.w;
-        if (v - 1 >= v_h) changes(v - 1, dlt(v - 1));
         // w[p] = S of column 4l - 5 + p of the previous row (p = 0 .. 13)
         int w[14];
 #pragma unroll
@@ -2713,7 +2700,7 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
         const int cap = std::min(16384, std::max(4096, 16 * d.W));   // staged road edges (bytes)
-        const size_t lw = sizeof(int) * (512 + kWave + 3 * (size_t)d.H + 2) + cap;
+        const size_t lw = sizeof(int) * (256 + 3 * (size_t)d.H + 2) + cap;
         const int wave_bytes = (int)((lw + 15) / 16 * 16);
         const int fpw = std::max(1, std::min(4, kMaxLds / wave_bytes));   // frames per workgroup
         allow_lds(k_vpx_window, (size_t)fpw * wave_bytes);
