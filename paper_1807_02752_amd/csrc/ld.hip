@@ -1734,6 +1734,7 @@ __global__ __launch_bounds__(kBlock) void k_seed(Dev d, int nb, int delta, int m
 constexpr int kWalkChunk = 32;
 
 __device__ __forceinline__ int shfl_i(int x, int src) { return __shfl(x, src, kWave); }
+__device__ __forceinline__ int min3_i(int a, int b, int c) { return min(min(a, b), c); }
 // x of lane l - 1 (kBig on lane 0) and of lane l + 1 (kBig on lane 63): DPP wave shifts by one
 __device__ __forceinline__ int lane_prev(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x138, 0xF, 0xF, false); }
 __device__ __forceinline__ int lane_next(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x130, 0xF, 0xF, false); }
@@ -1742,18 +1743,22 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     extern __shared__ unsigned char smem_all[];
     // blockDim.x / 64 frames per workgroup, one per wave with its own LDS slice: the waves of
     // a workgroup go to different SIMDs, so a batch of four frames per CU runs one wave per SIMD
-    const int b = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave, l = lane_id();
+    // the frame's values are wave-uniform: kept in scalar registers, so every loop below
+    // branches on scalars
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int b = (int)blockIdx.x * (int)(blockDim.x / kWave) + wv, l = lane_id();
     if (b >= nframes || frame_masked(d, b)) return;
-    unsigned char* smem = smem_all + (size_t)(threadIdx.x / kWave) * wave_bytes;
+    unsigned char* smem = smem_all + (size_t)wv * wave_bytes;
     int32_t* pr = d.prune + (int64_t)b * kPruneWords;
-    if (pr[1] & kFbPlainVpx) return;
+    if (__builtin_amdgcn_readfirstlane(pr[1]) & kFbPlainVpx) return;
     const int H = d.H, W2 = d.W2, v_max = H - 1;
     FrameInfo fi = d.info[b];
     for (int v = l; v < H; v += kWave) d.mxpath[(int64_t)b * H + v] = -1;
-    const int v_h = fi.v_h, chi = d.P.chi, R = v_max - v_h + 1;
-    const int lo = pr[3], hi = pr[4], win = hi - lo + 1;
-    int* dlt = reinterpret_cast<int*>(smem);                 // 256 band deltas of a row
-    int* cntL = dlt + 256;                                    // H
+    const int v_h = __builtin_amdgcn_readfirstlane(fi.v_h), chi = d.P.chi, R = v_max - v_h + 1;
+    const int lo = __builtin_amdgcn_readfirstlane(pr[3]), hi = __builtin_amdgcn_readfirstlane(pr[4]);
+    const int win = hi - lo + 1;
+    int* dlt = reinterpret_cast<int*>(smem);                 // 256 band deltas of a row + 64 lane sinks
+    int* cntL = dlt + 256 + kWave;                            // H
     int* path = cntL + H;                                     // H + 1 (the last: touch flag)
     int* roff = path + H + 1;                                 // R + 1 <= H + 1
     uint8_t* wb = reinterpret_cast<uint8_t*>(roff + H + 1);               // stage_cap bytes
@@ -1776,7 +1781,7 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         }
         if (l == 0) roff[R] = carry;
     }
-    const int ne = roff[R];
+    const int ne = __builtin_amdgcn_readfirstlane(roff[R]);
     // window offset of every road edge's vote column (255: outside the window or no vote),
     // loaded eight rows at a time with every load of the group in flight
     const bool staged = ne <= stage_cap;
@@ -1848,77 +1853,27 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
             if (key >= 0) atomicAdd(&dlt[key], sign);
         }
     };
-    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 1);
-    // S = 16 E of the own columns (kBig outside the window).  A candidate from column c + tau
-    // costs S(c + tau) + slope |tau| - [tau < 0] with slope = 16 lambda + 2, i.e. 16 (E + lambda
-    // |tau|) plus the rank of tau in the tie order 0, -1, +1, -2, +2, ..., so one min picks the
-    // cost and the tie; offsets are taken relative to the lane's first column 4l.
-    int h[4], S[4];
+    for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 16);
+    // S = 16 E of the own columns (kBig outside the window), H = 16 x the column's band count
+    // (the deltas are applied in units of 16).  A candidate from column c + tau costs
+    // S(c + tau) + slope |tau| - [tau < 0] with slope = 16 lambda + 2, i.e. 16 (E + lambda |tau|)
+    // plus the rank of tau in the tie order 0, -1, +1, -2, +2, ..., so one min picks the cost
+    // and the tie; offsets are taken relative to the lane's first column 4l.
+    int Hc[4], S[4];
+    bool inw[4];
     {
         const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
-        h[0] = q.x; h[1] = q.y; h[2] = q.z; h[3] = q.w;
+        Hc[0] = q.x; Hc[1] = q.y; Hc[2] = q.z; Hc[3] = q.w;
         *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) S[j] = 4 * l + j < win ? -16 * h[j] : kBig;
+    for (int j = 0; j < 4; ++j) {
+        inw[j] = 4 * l + j < win;
+        S[j] = inw[j] ? -Hc[j] : kBig;
+    }
     const int tau_max = d.P.tau_x_max, slope = 16 * d.P.lambda_x + 2;
-    const bool full5 = tau_max == 5;
-    // With the vote columns staged, the band changes of row v (votes of row v - chi entering,
-    // of row v + chi + 1 leaving) are read ahead: the list heads (count, offset) two rows
-    // ahead and the first 64 window offsets of each list one row ahead, so a row waits for
-    // one LDS round trip (its deltas) before the DP.
-    int nA2 = 0, oA2 = 0, nR2 = 0, oR2 = 0;        // list heads of row v - 1
-    int nA1 = 0, oA1 = 0, nR1 = 0, oR1 = 0;        // list heads of row v
-    int kA = -1, kR = -1;                          // own entries of row v's lists (-1: none)
-    auto heads = [&](int r, int& nA, int& oA, int& nR, int& oR) {
-        const int ra = r - chi, rr = r + chi + 1;
-        nA = (r >= v_h && ra >= v_h) ? cntL[max(ra, 0)] : 0;
-        oA = roff[max(ra - v_h, 0)];
-        nR = (r >= v_h && rr <= v_max) ? cntL[min(rr, v_max)] : 0;
-        oR = roff[min(max(rr - v_h, 0), R)];
-    };
-    auto own_key = [&](int n, int o) -> int {
-        if (l >= n) return -1;
-        const int c = wb[o + l];
-        return c != 255 ? c : -1;
-    };
-    if (staged) {
-        heads(v_max - 1, nA1, oA1, nR1, oR1);
-        heads(v_max - 2, nA2, oA2, nR2, oR2);
-        kA = own_key(nA1, oA1);
-        kR = own_key(nR1, oR1);
-    }
-    for (int v = v_max - 1; v >= v_h; --v) {
-        if (staged) {
-            if (kA >= 0) atomicAdd(&dlt[kA], 1);
-            if (kR >= 0) atomicAdd(&dlt[kR], -1);
-            // long lists: four offsets read before their atomics
-            for (int i0 = l + kWave; i0 < max(nA1, nR1); i0 += 2 * kWave) {
-                int ca[2], cr[2];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int i = i0 + j * kWave;
-                    ca[j] = i < nA1 ? wb[oA1 + i] : 255;
-                    cr[j] = i < nR1 ? wb[oR1 + i] : 255;
-                }
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    if (ca[j] != 255) atomicAdd(&dlt[ca[j]], 1);
-                    if (cr[j] != 255) atomicAdd(&dlt[cr[j]], -1);
-                }
-            }
-            kA = own_key(nA2, oA2);                 // row v - 1
-            kR = own_key(nR2, oR2);
-            nA1 = nA2; oA1 = oA2; nR1 = nR2; oR1 = oR2;
-            heads(v - 2, nA2, oA2, nR2, oR2);
-        } else {
-            if (v - chi >= v_h) apply(v - chi, 1);
-            if (v + chi + 1 <= v_max) apply(v + chi + 1, -1);
-        }
-        // the wave's LDS operations complete in order: the deltas are final here
-        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
-        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
-        h[0] += q.x; h[1] += q.y; h[2] += q.z; h[3] += q.w;
+    // one row of the DP from the previous row's S and this row's H (returns the 4-bit ranks)
+    auto dp_row = [&]() -> uint32_t {
         // w[p] = S of column 4l - 5 + p of the previous row (p = 0 .. 13)
         int w[14];
 #pragma unroll
@@ -1929,32 +1884,100 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         }
         w[0] = lane_prev(w[4]);
         w[13] = lane_next(w[9]);
-        int TL[14], TR[14];
+        int lm[4], rm[4];
+        if (tau_max == 5) {
+            // TL[p] = w[p] + slope (5 - p) for p = 0 .. 7 and TR[p] = w[p] + slope (p - 5) for
+            // p = 6 .. 13; the minima over five consecutive entries share their middle terms
+            int TL[8], TR[8];
 #pragma unroll
-        for (int p = 0; p < 14; ++p) {
-            const int off = slope * (p - 5);
-            TL[p] = w[p] - off;
-            TR[p] = w[p] + off;
+            for (int p = 0; p < 8; ++p) {
+                TL[p] = w[p] + slope * (5 - p);
+                TR[p] = w[p + 6] + slope * (p + 1);
+            }
+            const int cl = min3_i(TL[2], TL[3], TL[4]);
+            lm[0] = min3_i(TL[0], TL[1], cl);
+            lm[1] = min3_i(TL[1], cl, TL[5]);
+            lm[2] = min3_i(cl, TL[5], TL[6]);
+            lm[3] = min3_i(TL[3], TL[4], min3_i(TL[5], TL[6], TL[7]));
+            const int cr = min3_i(TR[2], TR[3], TR[4]);
+            rm[0] = min3_i(TR[0], TR[1], cr);
+            rm[1] = min3_i(TR[1], cr, TR[5]);
+            rm[2] = min3_i(cr, TR[5], TR[6]);
+            rm[3] = min3_i(TR[3], TR[4], min3_i(TR[5], TR[6], TR[7]));
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                lm[j] = kBig; rm[j] = kBig;
+#pragma unroll
+                for (int a = 1; a <= 5; ++a)
+                    if (a <= tau_max) {
+                        lm[j] = min(lm[j], w[j + 5 - a] + slope * (a - j));
+                        rm[j] = min(rm[j], w[j + 5 + a] + slope * (a + j));
+                    }
+            }
         }
         uint32_t bits = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int lm, rm;
-            if (full5) {
-                lm = min(min(min(TL[j], TL[j + 1]), min(TL[j + 2], TL[j + 3])), TL[j + 4]);
-                rm = min(min(min(TR[j + 6], TR[j + 7]), min(TR[j + 8], TR[j + 9])), TR[j + 10]);
-            } else {
-                lm = kBig; rm = kBig;
-#pragma unroll
-                for (int a = 1; a <= 5; ++a)
-                    if (a <= tau_max) { lm = min(lm, TL[j + 5 - a]); rm = min(rm, TR[j + 5 + a]); }
-            }
-            const int cc = slope * j;
-            const int key = min(w[5 + j], min(lm + (cc - 1), rm - cc));
-            S[j] = 4 * l + j < win ? (key & ~15) - 16 * h[j] : kBig;
+            const int key = min3_i(w[5 + j], lm[j] + (slope * j - 1), rm[j] - slope * j);
+            S[j] = inw[j] ? (key & ~15) - Hc[j] : kBig;
             bits |= (uint32_t)(key & 15) << (4 * j);
         }
-        back[(int64_t)(v - v_h) * kWave + l] = (uint16_t)bits;
+        return bits;
+    };
+    auto take_deltas = [&]() {
+        // the wave's LDS operations complete in order: the deltas are final here
+        const int4 q = *reinterpret_cast<const int4*>(dlt + 4 * l);
+        *reinterpret_cast<int4*>(dlt + 4 * l) = make_int4(0, 0, 0, 0);
+        Hc[0] += q.x; Hc[1] += q.y; Hc[2] += q.z; Hc[3] += q.w;
+    };
+    if (staged) {
+        // Row v (v = v_max - 1 - t) adds the votes of row v - chi and removes those of row
+        // v + chi + 1.  Lane l holds the two lists' heads (offset << 16 | count) of row
+        // t0 + l of the current 64-row chunk, taken by readlane; the own entries of the next
+        // row's lists are read while the current row is computed.  Lanes without an entry
+        // add to their own sink word.
+        int* sink = dlt + 256 + l;
+        auto heads = [&](int t0, int& hA, int& hR) {
+            const int v = v_max - 1 - t0 - l, ra = v - chi, rr = v + chi + 1;
+            hA = (v >= v_h && ra >= v_h) ? (roff[ra - v_h] << 16 | cntL[ra]) : 0;
+            hR = (v >= v_h && rr <= v_max) ? (roff[rr - v_h] << 16 | cntL[rr]) : 0;
+        };
+        auto own_slot = [&](int hd) -> int* {
+            const int n = hd & 0xFFFF, o = hd >> 16;
+            const int c = wb[l < n ? o + l : 0];
+            return (l < n && c != 255) ? dlt + c : sink;
+        };
+        int hA, hR;
+        heads(0, hA, hR);
+        int* pA = own_slot(__builtin_amdgcn_readlane(hA, 0));
+        int* pR = own_slot(__builtin_amdgcn_readlane(hR, 0));
+        for (int t = 0; t < R - 1; ++t) {
+            const int v = v_max - 1 - t;
+            const int cA = __builtin_amdgcn_readlane(hA, t & 63), cR = __builtin_amdgcn_readlane(hR, t & 63);
+            atomicAdd(pA, 16);
+            atomicAdd(pR, -16);
+            const int nA = cA & 0xFFFF, nR = cR & 0xFFFF;
+            for (int i0 = kWave; i0 < max(nA, nR); i0 += kWave) {     // long lists
+                const int i = i0 + l;
+                const int ca = i < nA ? wb[(cA >> 16) + i] : 255;
+                const int cr = i < nR ? wb[(cR >> 16) + i] : 255;
+                atomicAdd(ca != 255 ? dlt + ca : sink, 16);
+                atomicAdd(cr != 255 ? dlt + cr : sink, -16);
+            }
+            if (((t + 1) & 63) == 0) heads(t + 1, hA, hR);
+            pA = own_slot(__builtin_amdgcn_readlane(hA, (t + 1) & 63));
+            pR = own_slot(__builtin_amdgcn_readlane(hR, (t + 1) & 63));
+            take_deltas();
+            back[(int64_t)(v - v_h) * kWave + l] = (uint16_t)dp_row();
+        }
+    } else {
+        for (int v = v_max - 1; v >= v_h; --v) {
+            if (v - chi >= v_h) apply(v - chi, 16);
+            if (v + chi + 1 <= v_max) apply(v + chi + 1, -16);
+            take_deltas();
+            back[(int64_t)(v - v_h) * kWave + l] = (uint16_t)dp_row();
+        }
     }
     // start column: argmin over the window of E at v_h, ties to the smaller column
     int64_t bv = INT64_MAX;
@@ -2700,7 +2723,7 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     if (s == LD_OK) {
         ProfScope ps(f, 8, st);
         const int cap = std::min(16384, std::max(4096, 16 * d.W));   // staged road edges (bytes)
-        const size_t lw = sizeof(int) * (256 + 3 * (size_t)d.H + 2) + cap;
+        const size_t lw = sizeof(int) * (256 + kWave + 3 * (size_t)d.H + 2) + cap;
         const int wave_bytes = (int)((lw + 15) / 16 * 16);
         const int fpw = std::max(1, std::min(4, kMaxLds / wave_bytes));   // frames per workgroup
         allow_lds(k_vpx_window, (size_t)fpw * wave_bytes);
