@@ -224,7 +224,8 @@ const char* ld_status_string(ld_status s);
  *                      seed column c_s (-1 none), window lo, hi, pooled marking votes,
  *                      per-band argmax column [4] (-1 none), per-band votes [4], kept
  *                      candidates, 0
- *   LD_STATE_CAND_MASK uint8[2 * width]: candidate mask of the last ld_detect_pruned */
+ *   LD_STATE_CAND_MASK uint8[2 * width]: candidate mask of the last ld_detect_pruned that pruned
+ *     candidates (dilate >= 0); all ones before the first such call */
 enum {
     LD_STATE_INFO = 0, LD_STATE_MY_PATH = 1, LD_STATE_BETA = 2, LD_STATE_GAMMA = 3, LD_STATE_TABLES = 4,
     LD_STATE_ROWCOUNT = 5, LD_STATE_EDGES = 6, LD_STATE_MX_PATH = 7, LD_STATE_ENERGY = 8, LD_STATE_TRACE = 9,

@@ -989,6 +989,12 @@ __device__ __forceinline__ void band_apply(const int* bins, int sign, int* hist,
 }
 
 __device__ __forceinline__ int rank_to_tau(int r) { return r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1)); }
+// rank_to_tau(r) + 8 in bits 4r .. 4r+3 for r = 0 .. 10
+constexpr uint64_t kRankTau = [] {
+    uint64_t x = 0;
+    for (int r = 0; r <= 10; ++r) x |= (uint64_t)((r == 0 ? 0 : ((r & 1) ? -((r + 1) >> 1) : (r >> 1))) + 8) << (4 * r);
+    return x;
+}();
 
 // S8: RANSAC of the quartic through the path points (PX = rows, PY = u columns), V_px and the
 // track tables, frame info.
@@ -1738,6 +1744,10 @@ __device__ __forceinline__ int min3_i(int a, int b, int c) { return min(min(a, b
 // x of lane l - 1 (kBig on lane 0) and of lane l + 1 (kBig on lane 63): DPP wave shifts by one
 __device__ __forceinline__ int lane_prev(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x138, 0xF, 0xF, false); }
 __device__ __forceinline__ int lane_next(int x) { return __builtin_amdgcn_update_dpp(kBig, x, 0x130, 0xF, 0xF, false); }
+// the same shifts filling with 0 (lane 0, lane 63)
+__device__ __forceinline__ int lane_prev0(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ int lane_next0(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
+constexpr int kBig16 = 0x3FFFFFF0;
 
 __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wave_bytes, int nframes) {
     extern __shared__ unsigned char smem_all[];
@@ -1764,12 +1774,21 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     uint8_t* wb = reinterpret_cast<uint8_t*>(roff + H + 1);               // stage_cap bytes
     uint16_t* back = reinterpret_cast<uint16_t*>(d.back_x) + (int64_t)b * H * ((W2 + kDpRun - 1) / kDpRun) * 2;
     const ld_edge* fe = d.edges + (int64_t)b * H * d.W;
-    for (int v = l; v < H; v += kWave) cntL[v] = d.rowcnt[(int64_t)b * H + v];
+    // the road rows' edge counts (the search reads no other row), eight loads per lane in
+    // flight before the first is stored
+    for (int base = 0; base < R; base += 8 * kWave) {
+        int cn[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cn[k] = d.rowcnt[(int64_t)b * H + v_h + min(base + k * kWave + l, R - 1)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (base + k * kWave + l < R) cntL[v_h + base + k * kWave + l] = cn[k];
+    }
     for (int i = l; i < 256; i += kWave) dlt[i] = 0;
     {   // exclusive prefix of the road rows' edge counts, 64 rows per wave scan
         int carry = 0;
         for (int base = 0; base < R; base += kWave) {
-            const int own = base + l < R ? d.rowcnt[(int64_t)b * H + v_h + base + l] : 0;
+            const int own = base + l < R ? cntL[v_h + base + l] : 0;
             int x = own;
 #pragma unroll
             for (int o = 1; o < kWave; o <<= 1) {
@@ -1788,47 +1807,67 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     auto woff = [&](int c) -> uint8_t { return (c >= lo && c <= hi) ? (uint8_t)(c - lo) : (uint8_t)255; };
     int nv = 0;
     if (staged) {
-        // the next group of 16 rows is loaded while the current one is written to LDS
-        int c2[16][2];
-        auto load_group = [&](int v0, int (&c)[16][2]) {
+        // Groups of 16 rows, two in flight while a third is written to LDS: lane l loads the
+        // vote columns of entries l and l + 64 of every row of a group (the window search needs
+        // W >= 128, so both lie in the row's slots; entries past the row's count and rows past
+        // v_max, read as row v_max, are loaded and not used).  The two register sets are
+        // written in turn, so no copy waits on loads in flight.  Lane l holds the count and
+        // offset (offset << 16 | count) of row v_h + 64 m + l of the current 64-row chunk m.
+        uint8_t* junk = reinterpret_cast<uint8_t*>(dlt + 256 + l);   // stores of lanes without an entry
+        const int ng = (R + 15) / 16;
+        auto load_group = [&](int g, int (&c)[16][2]) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const int v = v0 + k, n = v <= v_max ? cntL[v] : 0;
-                c[k][0] = l < n ? fe[(int64_t)v * d.W + l].bin : -1;
-                c[k][1] = l + kWave < n ? fe[(int64_t)v * d.W + l + kWave].bin : -1;
+                const ld_edge* row = fe + (int64_t)min(v_h + 16 * g + k, v_max) * d.W;
+                c[k][0] = row[l].bin;
+                c[k][1] = row[l + kWave].bin;
             }
         };
-        load_group(v_h, c2);
-        for (int v0 = v_h; v0 <= v_max; v0 += 16) {
-            int cg[16][2];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) { cg[k][0] = c2[k][0]; cg[k][1] = c2[k][1]; }
-            if (v0 + 16 <= v_max) load_group(v0 + 16, c2);
+        int desc = 0;
+        auto store_group = [&](int g, const int (&c)[16][2]) {
+            if ((g & 3) == 0) {
+                const int r = 16 * g + l;
+                desc = r < R ? (roff[r] << 16 | cntL[v_h + r]) : 0;
+            }
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const int v = v0 + k;
-                if (v > v_max) break;
-                const int n = cntL[v], o = roff[v - v_h];
-                nv += (cg[k][0] >= 0 ? 1 : 0) + (cg[k][1] >= 0 ? 1 : 0);
-                if (l < n) wb[o + l] = woff(cg[k][0]);
-                if (l + kWave < n) wb[o + l + kWave] = woff(cg[k][1]);
-                for (int i0 = l + 2 * kWave; i0 < n; i0 += 8 * kWave) {   // long rows: 8 loads in flight
-                    int cc[8];
+                const int r = 16 * g + k;
+                if (r >= R) break;
+                const int rd = __builtin_amdgcn_readlane(desc, r & 63);
+                const int n = rd & 0xFFFF, o = rd >> 16;
+                const bool e0 = l < n, e1 = l + kWave < n;
+                nv += (e0 && c[k][0] >= 0 ? 1 : 0) + (e1 && c[k][1] >= 0 ? 1 : 0);
+                *(e0 ? wb + o + l : junk) = woff(c[k][0]);
+                *(e1 ? wb + o + l + kWave : junk) = woff(c[k][1]);
+                if (n > 2 * kWave) {                 // long rows: 8 loads in flight
+                    const int v = v_h + r;
+                    for (int i0 = l + 2 * kWave; i0 < n; i0 += 8 * kWave) {
+                        int cc[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int i = i0 + j * kWave;
-                        cc[j] = i < n ? fe[(int64_t)v * d.W + i].bin : -1;
-                    }
+                        for (int j = 0; j < 8; ++j) {
+                            const int i = i0 + j * kWave;
+                            cc[j] = i < n ? fe[(int64_t)v * d.W + i].bin : -1;
+                        }
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int i = i0 + j * kWave;
-                        if (i < n) {
-                            nv += cc[j] >= 0 ? 1 : 0;
-                            wb[o + i] = woff(cc[j]);
+                        for (int j = 0; j < 8; ++j) {
+                            const int i = i0 + j * kWave;
+                            if (i < n) {
+                                nv += cc[j] >= 0 ? 1 : 0;
+                                wb[o + i] = woff(cc[j]);
+                            }
                         }
                     }
                 }
             }
+        };
+        int ca[16][2], cb[16][2];
+        load_group(0, ca);
+        load_group(1, cb);
+        for (int g = 0; g < ng; g += 2) {
+            store_group(g, ca);
+            load_group(g + 2, ca);
+            if (g + 1 < ng) store_group(g + 1, cb);
+            load_group(g + 3, cb);
         }
     } else {
         for (int v = v_h; v <= v_max; ++v)
@@ -1854,8 +1893,11 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         }
     };
     for (int r = max(v_max - chi, v_h); r <= v_max; ++r) apply(r, 16);
-    // S = 16 E of the own columns (kBig outside the window), H = 16 x the column's band count
-    // (the deltas are applied in units of 16).  A candidate from column c + tau costs
+    // S = 16 E of the own columns (kBig16 outside the window), H = 16 x the column's band count
+    // (the deltas are applied in units of 16); the registers hold S - kBig16, so the columns
+    // outside the window and beyond the wave's ends are 0 and the wave shifts fill with 0.
+    // kBig16 is a multiple of 16, so the rank bits and the update below are unchanged by the
+    // offset, and it exceeds every reachable |16 E|.  A candidate from column c + tau costs
     // S(c + tau) + slope |tau| - [tau < 0] with slope = 16 lambda + 2, i.e. 16 (E + lambda |tau|)
     // plus the rank of tau in the tie order 0, -1, +1, -2, +2, ..., so one min picks the cost
     // and the tie; offsets are taken relative to the lane's first column 4l.
@@ -1869,7 +1911,7 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         inw[j] = 4 * l + j < win;
-        S[j] = inw[j] ? -Hc[j] : kBig;
+        S[j] = inw[j] ? -Hc[j] - kBig16 : 0;
     }
     const int tau_max = d.P.tau_x_max, slope = 16 * d.P.lambda_x + 2;
     // one row of the DP from the previous row's S and this row's H (returns the 4-bit ranks)
@@ -1878,12 +1920,12 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         int w[14];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            w[1 + j] = lane_prev(S[j]);
+            w[1 + j] = lane_prev0(S[j]);
             w[5 + j] = S[j];
-            w[9 + j] = lane_next(S[j]);
+            w[9 + j] = lane_next0(S[j]);
         }
-        w[0] = lane_prev(w[4]);
-        w[13] = lane_next(w[9]);
+        w[0] = lane_prev0(w[4]);
+        w[13] = lane_next0(w[9]);
         int lm[4], rm[4];
         if (tau_max == 5) {
             // TL[p] = w[p] + slope (5 - p) for p = 0 .. 7 and TR[p] = w[p] + slope (p - 5) for
@@ -1907,7 +1949,7 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                lm[j] = kBig; rm[j] = kBig;
+                lm[j] = 0; rm[j] = 0;
 #pragma unroll
                 for (int a = 1; a <= 5; ++a)
                     if (a <= tau_max) {
@@ -1920,7 +1962,7 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int key = min3_i(w[5 + j], lm[j] + (slope * j - 1), rm[j] - slope * j);
-            S[j] = inw[j] ? (key & ~15) - Hc[j] : kBig;
+            S[j] = inw[j] ? (key & ~15) - Hc[j] : 0;
             bits |= (uint32_t)(key & 15) << (4 * j);
         }
         return bits;
@@ -1990,8 +2032,7 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
     // Walk: the backtrace words of kWalkChunk rows in registers (lane l holds columns
     // 4l .. 4l+3 of each row) with the next chunk in flight; the column is wave-uniform, so a
     // step is a readlane and a few scalar operations.  Lane r keeps the path of row v0 + r.
-    int c = bc, touch = 0;
-    uint32_t bk[kWalkChunk], bn[kWalkChunk];
+    int c = __builtin_amdgcn_readfirstlane(bc), touch = 0;
     auto load_chunk = [&](int v0, uint32_t (&dst)[kWalkChunk]) {
 #pragma unroll
         for (int r = 0; r < kWalkChunk; ++r) {
@@ -1999,26 +2040,40 @@ __global__ __launch_bounds__(256) void k_vpx_window(Dev d, int stage_cap, int wa
             dst[r] = back[(int64_t)max(v - v_h, 0) * kWave + l];
         }
     };
-    load_chunk(v_h, bk);
-    for (int v0 = v_h; v0 <= v_max; v0 += kWalkChunk) {
-        load_chunk(v0 + kWalkChunk, bn);          // clamped: always a full chunk of loads
+    auto walk_chunk = [&](int v0, const uint32_t (&bk)[kWalkChunk]) {
         int pv = 0;
 #pragma unroll
         for (int r = 0; r < kWalkChunk; ++r) {
             const int v = v0 + r;
             if (v <= v_max) {
-                if ((lo > 0 && c == 0) || (hi < W2 - 1 && c == win - 1)) touch = 1;
                 if (l == r) pv = lo + c;
                 if (v < v_max) {
                     const uint32_t word = __builtin_amdgcn_readlane(bk[r], c >> 2);
-                    c += rank_to_tau((int)((word >> (4 * (c & 3))) & 15u));
+                    const int rank = (int)((word >> (4 * (c & 3))) & 15u);
+                    c += (int)((kRankTau >> (4 * rank)) & 15u) - 8;
                 }
             }
         }
         if (l < kWalkChunk && v0 + l <= v_max) path[v0 + l] = pv;
-#pragma unroll
-        for (int r = 0; r < kWalkChunk; ++r) bk[r] = bn[r];
+    };
+    // two chunks in flight, the register sets written in turn (row loads are clamped, so
+    // every chunk is a full set of loads)
+    uint32_t ba[kWalkChunk], bb[kWalkChunk];
+    load_chunk(v_h, ba);
+    load_chunk(v_h + kWalkChunk, bb);
+    for (int v0 = v_h; v0 <= v_max; v0 += 2 * kWalkChunk) {
+        walk_chunk(v0, ba);
+        load_chunk(v0 + 2 * kWalkChunk, ba);
+        if (v0 + kWalkChunk <= v_max) walk_chunk(v0 + kWalkChunk, bb);
+        load_chunk(v0 + 3 * kWalkChunk, bb);
     }
+    // the path touches an inner edge of the window (a column the window cut off could have
+    // been reached): the frame goes back to the full search
+    for (int v = v_h + l; v <= v_max; v += kWave) {
+        const int pc = path[v];
+        if ((lo > 0 && pc == lo) || (hi < W2 - 1 && pc == hi)) touch = 1;
+    }
+    touch = __any(touch) ? 1 : 0;
     nv = wave_sum_i32(nv);
     if (touch) {
         if (l == 0) pr[1] |= kFbPlainVpx | kFbTouch;
@@ -2115,6 +2170,7 @@ __global__ void k_lane_check(Dev d, ld_lanes* lanes, int nframes, int pruning) {
     const uint8_t* cm = d.cmask + (int64_t)b * d.W2;
     int fb = pr[1];
     const FrameInfo fi = d.info[b];
+    if (!pruning) pr[14] = d.W2;        // candidates kept: all
     if (pruning && !(fb & kFbPlainVpx) && !(fi.flags & (LD_FLAG_NOROAD | LD_FLAG_NOVP))) {
         const int n = lanes[b].n;
         bool bad = n == 0;
@@ -2737,27 +2793,30 @@ ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t gr
     full.only_set = 1;
     if (s == LD_OK) s = run_vpx_dp(f, full, st);
     if (s == LD_OK) s = run_vpx_ransac(f, stream_ids, frame_idx, seed_gamma, 1, nullptr, st);
-    if (s == LD_OK) {
+    // without candidate pruning every candidate is kept: no mask, and no frame is sent back
+    // to the full energies
+    const bool pruning = c->dilate >= 0;
+    if (s == LD_OK && pruning) {
         ProfScope ps(f, 9, st);
         const size_t lm = sizeof(uint32_t) * nb * LDI_BAND_ROWS * (size_t)((d.W + 31) / 32) + (size_t)d.W2;
         allow_lds(k_cand_mask, lm);
         hipLaunchKernelGGL(k_cand_mask, dim3(f->active), dim3(kBlock), lm, st, d, nb, c->dilate);
         s = launch_ok();
     }
-    if (s == LD_OK) s = run_energy(f, d.cmask, nullptr, st);
+    if (s == LD_OK) s = run_energy(f, pruning ? d.cmask : nullptr, nullptr, st);
     if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st);
     if (s == LD_OK) {
         ProfScope ps(f, 9, st);
         hipLaunchKernelGGL(k_lane_check, dim3((f->active + 63) / 64), dim3(64), 0, st, d, lanes_out, f->active,
-                           c->dilate >= 0 ? 1 : 0);
+                           pruning ? 1 : 0);
         s = launch_ok();
     }
     Dev again = d;                      // frames sent back to the full energies
     again.only = d.prune;
     again.only_bits = kFbPlainEnergy;
     again.only_set = 1;
-    if (s == LD_OK) s = run_energy(f, nullptr, nullptr, st, &again);
-    if (s == LD_OK) s = run_peaks(f, lanes_out, curves_out, st, &again);
+    if (s == LD_OK && pruning) s = run_energy(f, nullptr, nullptr, st, &again);
+    if (s == LD_OK && pruning) s = run_peaks(f, lanes_out, curves_out, st, &again);
     f->stage = s == LD_OK ? 3 : 0;
     if (s == LD_OK) f->bands = nb;
     return s;
