@@ -286,7 +286,7 @@ typedef struct ld_cnn_s* ld_cnn;
 typedef struct ld_cnn_config {
     int32_t n_bands;      /* bands of 16 rows per frame, 1..4 (default 1) */
     float theta;          /* marking probability threshold, (0, 1) (0.5) */
-    int32_t delta_x;      /* half width of the V_px search window around the seed, 1..127 (112) */
+    int32_t delta_x;      /* half width of the V_px search window around the seed, 1..127 (127) */
     int32_t dilate;       /* candidates kept on each side of a candidate whose track hits
                              marking, 0..64; -1 (default) keeps every candidate */
     int32_t min_votes;    /* fewest marking votes that make a seed (8) */

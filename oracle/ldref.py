@@ -349,7 +349,7 @@ class Learned(C.Structure):
                 ("lane_bits", C.c_void_p), ("prune", C.c_int32 * 16), ("cand_mask", C.c_void_p)]
 
 
-def detect_pruned(grey: np.ndarray, disp: np.ndarray, d_max: int, lane_bits: np.ndarray, *, n_bands=1, delta_x=112,
+def detect_pruned(grey: np.ndarray, disp: np.ndarray, d_max: int, lane_bits: np.ndarray, *, n_bands=1, delta_x=127,
                   dilate=-1, min_votes=8, seed_ransac=0, params: Params | None = None, stream_id=0, frame_idx=0,
                   seed_gamma=None, want_m1=False):
     """The narrowed search given the network's band decisions lane_bits (4 x 16 x W u8):

@@ -905,7 +905,7 @@ void ld_cnn_config_default(ld_cnn_config* c) {
     if (!c) return;
     c->n_bands = 1;
     c->theta = 0.5f;
-    c->delta_x = 112;
+    c->delta_x = 127;
     c->dilate = -1;
     c->min_votes = 8;
     c->max_batch = 32;

@@ -167,9 +167,9 @@ def _vpx_gt(sc, v):
 def test_seed_of_ideal_marking_is_the_vanishing_point(seq, idx):
     """Edges marked by an ideal network (the scene's markings) vote for the scene's V_px.  A
     single row's votes scatter (the Sobel angle error of a marking edge is multiplied by
-    (1 + slope^2)(v - V_py)), so the seed is a coarse estimate: it must lie within half of the
-    default window (112 columns each side) of V_px at the band's rows, which leaves the true
-    path inside the window."""
+    (1 + slope^2)(v - V_py)), so the seed is a coarse estimate: it must lie within 56 columns
+    (less than half of the default window, 127 columns each side) of V_px at the band's rows,
+    which leaves the true path inside the window."""
     greys, disps, scenes = synth.make_batch("c2", seq, 1, idx)
     sc = scenes[0]
     g, d = greys[0], disps[0]
