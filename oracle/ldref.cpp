@@ -444,6 +444,52 @@ int ldref_sobel(const uint8_t* grey, int64_t pitch, int W, int H, int32_t* gx, i
 }
 
 // ------------------------------------------------------------------------------------
+// Bilateral pre-filter (Sec. 2.3.1, Eq. bilateral_filter and the two weights defined after
+// it): I_bf(u, v) = sum w_s w_r I / sum w_s w_r over the (2 rho + 1) x (2 rho + 1) window
+// centred at (u, v), w_s = exp(-((i-u)^2 + (j-v)^2) / sigma_s^2) on the offset and
+// w_r = exp(-(I(i,j) - I(u,v))^2 / sigma_r^2) on intensities scaled to [0, 1].
+// Readings (B1..B4): window pixels outside the frame take part in neither sum (B1); sigma_s and
+// sigma_r are single-precision numbers, and both weights are single-precision tables -- w_s per
+// window offset, w_r per absolute grey difference 0..255 -- each the double-precision
+// exponential rounded to float (B2); the sums run in single precision over the window row by
+// row (j), left to right (i), the numerator accumulated by a fused multiply-add of the product
+// weight with the intensity (B3); the output is the single-precision quotient rounded half up
+// to u8, so the gradient after it stays integer (B4).  Rows v < row0 are not written; val
+// (nullable, W x H) receives the quotients of the rows written.
+int ldref_bilateral(const uint8_t* grey, int64_t pitch, int W, int H, int rho, float sigma_s, float sigma_r,
+                    int row0, uint8_t* out, int64_t opitch, float* val) {
+    if (rho < 1 || rho > 5 || !(sigma_s > 0.0f) || !(sigma_r > 0.0f)) return -1;
+    const int n = 2 * rho + 1;
+    const double ss = (double)sigma_s, sr = (double)sigma_r;
+    std::vector<float> ws((size_t)n * n);
+    for (int dy = -rho; dy <= rho; ++dy)
+        for (int dx = -rho; dx <= rho; ++dx)
+            ws[(size_t)(dy + rho) * n + (dx + rho)] = (float)std::exp(-(double)(dx * dx + dy * dy) / (ss * ss));
+    float wr[256];
+    for (int d = 0; d < 256; ++d) {
+        const double x = (double)d / 255.0;
+        wr[d] = (float)std::exp(-(x * x) / (sr * sr));
+    }
+    for (int v = std::max(row0, 0); v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            const int c = grey[(int64_t)v * pitch + u];
+            float num = 0.0f, den = 0.0f;
+            for (int j = v - rho; j <= v + rho; ++j)
+                for (int i = u - rho; i <= u + rho; ++i) {
+                    if (i < 0 || i >= W || j < 0 || j >= H) continue;
+                    const int I = grey[(int64_t)j * pitch + i];
+                    const float w = ws[(size_t)(j - v + rho) * n + (i - u + rho)] * wr[std::abs(I - c)];
+                    num = std::fma(w, (float)I, num);
+                    den = den + w;
+                }
+            const float q = num / den;
+            if (val) val[(int64_t)v * W + u] = q;
+            out[(int64_t)v * opitch + u] = (uint8_t)std::floor(q + 0.5f);
+        }
+    return 0;
+}
+
+// ------------------------------------------------------------------------------------
 // Road mask + edges (Sec. 2.3.1): a pixel is on the road iff it is valid, lies on a road row
 // v_h <= v <= v_max and |D - f(v)| <= varpi; a road pixel is an edge iff
 // G_x^2 + G_y^2 > edge_t^2 (the magnitude read as Euclidean).  Edges are listed row-major.

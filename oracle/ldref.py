@@ -49,6 +49,7 @@ class FitOut(C.Structure):
 _P32 = C.POINTER(C.c_int32)
 _PD = C.POINTER(C.c_double)
 _P64 = C.POINTER(C.c_int64)
+_PF = C.POINTER(C.c_float)
 
 
 class Out(C.Structure):
@@ -84,6 +85,8 @@ def lib():
                                    C.c_uint64, C.c_uint64, C.c_int64, C.c_int, _PD, C.POINTER(FitOut), _P32]
         L.ldref_road_tables.argtypes = [C.POINTER(FitOut), C.c_int, _PD, _PD, _PD, _P32]
         L.ldref_sobel.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P32, _P32]
+        L.ldref_bilateral.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
+                                      C.c_int, C.c_void_p, C.c_int64, _PF]
         L.ldref_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, _P32]
         L.ldref_road_edges.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, _PD,
                                        C.c_int, C.c_double, C.c_int, _P32, _P32, _P32, _P32, C.c_int]
@@ -337,6 +340,21 @@ def sobel(grey: np.ndarray):
     gy = np.zeros((H, W), np.int32)
     lib().ldref_sobel(grey.ctypes.data, grey.strides[0], W, H, _p32(gx), _p32(gy))
     return gx, gy
+
+
+def bilateral(grey: np.ndarray, rho: int = 5, sigma_s: float = 300.0, sigma_r: float = 0.3, row0: int = 0):
+    """Bilateral pre-filter (Sec. 2.3.1, Eq. bilateral_filter): the u8 image and the float
+    quotients (rows below row0: 0 in both).  sigma_s and sigma_r are taken as float32."""
+    grey = np.ascontiguousarray(grey, dtype=np.uint8)
+    H, W = grey.shape
+    out = np.zeros((H, W), np.uint8)
+    val = np.zeros((H, W), np.float32)
+    rc = lib().ldref_bilateral(grey.ctypes.data, grey.strides[0], W, H, int(rho), float(np.float32(sigma_s)),
+                               float(np.float32(sigma_r)), int(row0), out.ctypes.data, W,
+                               val.ctypes.data_as(_PF))
+    if rc != 0:
+        raise ValueError("bilateral: invalid arguments")
+    return out, val
 
 
 class Result:
