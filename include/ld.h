@@ -167,6 +167,25 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
                     const uint64_t* stream_ids, const int64_t* frame_idx, ld_lanes* lanes_out, float* curves_out,
                     void* hip_stream);
 
+/* Bilateral pre-filter of the grey images ahead of the gradient (Sec. 2.3.1, Eq.
+ * bilateral_filter with its spatial weight w_s and range weight w_r): each output pixel is
+ * sum w_s w_r I / sum w_s w_r over the (2 rho + 1)^2 window around it, w_s = exp(-(du^2 + dv^2)
+ * / sigma_s^2), w_r = exp(-(dI / 255)^2 / sigma_r^2), window pixels outside the frame excluded,
+ * rounded half up to u8.  The arithmetic is fixed so the rounding is reproducible: FP32 weight
+ * tables (each the FP64 exponential of the float sigmas, rounded to float), FP32 sums in window
+ * order (rows top to bottom, each left to right; numerator by fused multiply-add), IEEE quotient.
+ * Pass `out` as the grey image of ld_vp_ransac / ld_detect / ld_detect_pruned to run the paper's
+ * pipeline with the filter.  The paper uses rho 5 (11 x 11), sigma_s 300, sigma_r 0.3.
+ *  grey, grey_pitch : device uint8 n x height x grey_pitch (n = active frames), >= width.
+ *  out, out_pitch   : device uint8 n x height x out_pitch, >= width; must not overlap grey.
+ *  rho              : 1..5.   sigma_s, sigma_r : finite, > 0.
+ *  road_rows        : 0 filters every row; 1 only rows v_h - 1 .. height - 1 of frames with a
+ *                     road (all that the later steps read of the grey image), after ld_vdisp on
+ *                     f (LD_E_STATE before it); the other rows of out are not written.
+ * LD_E_INVAL for invalid arguments or overlapping images; nothing is enqueued then. */
+ld_status ld_bilateral(ld_frame f, const uint8_t* grey, int64_t grey_pitch, uint8_t* out, int64_t out_pitch,
+                       int32_t rho, float sigma_s, float sigma_r, int32_t road_rows, void* hip_stream);
+
 /* Scratch of ld_detect_noalloc, per GPU (64 MiB). */
 #define LD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 

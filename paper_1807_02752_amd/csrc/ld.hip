@@ -2914,6 +2914,12 @@ ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v) {
     return LD_OK;
 }
 
+ld_status ldi_frame_set_last(ld_frame f, void* stream) {
+    if (!f) return LD_E_INVAL;
+    f->last = static_cast<hipStream_t>(stream);
+    return LD_OK;
+}
+
 ld_status ldi_frame_mark_bands(ld_frame f, int32_t n_bands, void* stream) {
     if (!f) return LD_E_INVAL;
     f->bands = n_bands;

@@ -35,6 +35,9 @@ typedef struct {
 
 ld_status ldi_frame_get_view(ld_frame f, ldi_frame_view* v);
 
+// Records `stream` as the one ld_sync of f waits for (work enqueued outside ld.hip).
+ld_status ldi_frame_set_last(ld_frame f, void* stream);
+
 // Marks that the band decisions of the frame were written on `stream` (after ld_vdisp).
 ld_status ldi_frame_mark_bands(ld_frame f, int32_t n_bands, void* stream);
 

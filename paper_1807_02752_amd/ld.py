@@ -134,6 +134,8 @@ def lib():
         L.ld_detect_noalloc.argtypes = [i32, i32, i32, i32, i32, C.POINTER(ld_params), vp, i64, vp, i64, vp, vp,
                                         vp, vp, vp]
         L.ld_detect_noalloc.restype = i32
+        L.ld_bilateral.argtypes = [vp, vp, i64, vp, i64, i32, C.c_float, C.c_float, i32, vp]
+        L.ld_bilateral.restype = i32
         for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
                      "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"):
             getattr(L, name).restype = i32
@@ -151,7 +153,7 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
             "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc",
-            "ld_cnn_save", "ld_cnn_load"]
+            "ld_cnn_save", "ld_cnn_load", "ld_bilateral"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -220,6 +222,10 @@ def ld_detect_noalloc(width, height, batch, fmt, d_max, params, grey, grey_pitch
 
 
 LD_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ld_bilateral(f, grey, grey_pitch, out, out_pitch, rho, sigma_s, sigma_r, road_rows, stream):
+    return lib().ld_bilateral(f, grey, grey_pitch, out, out_pitch, rho, sigma_s, sigma_r, road_rows, stream)
 
 
 def ld_sync(f):
@@ -481,6 +487,12 @@ class Detector:
         check(ld_detect(self.handle, _ptr(grey), self._pitch(grey), _ptr(disp), self._pitch(disp),
                         _ptr(stream_ids), _ptr(frame_idx), _ptr(lanes_out), _ptr(curves_out), _stream()),
               "ld_detect")
+
+    def bilateral(self, grey, out, rho: int = 5, sigma_s: float = 300.0, sigma_r: float = 0.3,
+                  road_rows: bool = False):
+        """Bilateral pre-filter of the grey images into `out` (uint8, same shape)."""
+        check(ld_bilateral(self.handle, _ptr(grey), self._pitch(grey), _ptr(out), self._pitch(out), int(rho),
+                           float(sigma_s), float(sigma_r), 1 if road_rows else 0, _stream()), "ld_bilateral")
 
     def sync(self):
         check(ld_sync(self.handle), "ld_sync")
