@@ -78,6 +78,7 @@ struct ldref_params {
     double rho_lpv;       // lane threshold as a fraction of the deepest minimum (R18): 0.25
     int32_t d_nms;        // minimum lane separation, 0 -> max(8, W/64) (R18)
     int32_t weight_squared;  // 0: exponent as printed, 1: squared (Gaussian) reading (R15)
+    int32_t vote;         // 0: q = G_x w_g (Sec. 2.4); 1: the prior work's vote (Sec. 2.4 opening)
     uint64_t seed;        // Philox key word 0 (R5)
 };
 
@@ -85,7 +86,7 @@ void ldref_params_default(ldref_params* p) {
     p->chi = 25; p->tau_y_max = 6; p->tau_x_max = 5; p->lambda_y = 1; p->lambda_x = 1;
     p->tr_y = 4.0; p->tr_x = 16.0; p->eps_num = 99; p->eps_den = 100; p->varpi = 3.0;
     p->edge_t = 100; p->sigma_g = 3.5; p->nu = 1; p->varsigma = 3; p->n_hyp = 64;
-    p->max_rounds = 16; p->rho_lpv = 0.25; p->d_nms = 0; p->weight_squared = 0; p->seed = 0;
+    p->max_rounds = 16; p->rho_lpv = 0.25; p->d_nms = 0; p->weight_squared = 0; p->vote = 0; p->seed = 0;
 }
 
 void ldref_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
@@ -594,8 +595,15 @@ int ldref_row_dp(const int64_t* mx, int H, int W2, int v_h, int tau_max, int lam
 // exact test dot^2 >= (3/4) |t|^2 |r|^2 (cos^2(pi/6) = 3/4).  R15: w_g = exp(-p / sigma_g^2)
 // with p = delta / theta_s, theta_s = pi/36, as printed (squared = 1: exp(-p^2 / sigma_g^2)).
 // q = G_x * w_g per edge.  Returns the number of edges that pass the gate.
+// vote = 1 (A/B variant): the vote of the authors' prior work named at the opening of Sec. 2.4,
+// V(e) = |grad(e)| cos(theta_e - theta_Vp), in place of G_x w_g.  R20: theta_e is the direction
+// of the tangent t = (-G_y, G_x) (the gradient turned by +90 degrees, so the two edges of a
+// marking point opposite ways) and theta_Vp the direction of the ray from V_p(v) to the pixel,
+// p - V_p = -r; then V(e) = t . (-r) / |r| = -dot / |r|, no gate, 0 at V_p itself.  On a lane
+// edge V(e) has the sign of G_x, so the box, M_1, the energies and the minima that follow are
+// the paper's, with the vote swapped.  Returns n.
 int ldref_weights(const int32_t* eu, const int32_t* ev, const int32_t* egx, const int32_t* egy, int n,
-                  const double* vpx, const double* vpy, double sigma_g, int squared, double* q) {
+                  const double* vpx, const double* vpy, double sigma_g, int squared, double* q, int vote) {
     const double pi = 3.14159265358979323846;
     const double theta_s = pi / 36.0;
     const double sg2 = sigma_g * sigma_g;
@@ -606,6 +614,11 @@ int ldref_weights(const int32_t* eu, const int32_t* ev, const int32_t* egx, cons
         double dot = tx * rx + ty * ry;
         double tt = tx * tx + ty * ty;
         double rr = rx * rx + ry * ry;
+        if (vote) {
+            q[i] = rr > 0.0 ? -dot / std::sqrt(rr) : 0.0;
+            ++kept;
+            continue;
+        }
         double w = 0.0;
         if (dot * dot >= (0.75 * tt) * rr) {
             double cr = tx * ry - ty * rx;
@@ -1053,7 +1066,7 @@ static int detect_impl(const uint8_t* grey, int64_t gpitch, const void* disp, in
     // S9: weights q = G_x w_g on the road edges, scattered into an image-sized map
     std::vector<double> eq(ne > 0 ? ne : 1, 0.0);
     ldref_weights(eu.data(), ev.data(), egx.data(), egy.data(), ne, vpx.data(), vpy.data(), P->sigma_g,
-                  P->weight_squared, eq.data());
+                  P->weight_squared, eq.data(), P->vote);
     std::vector<double> q((size_t)H * W, 0.0);
     for (int i = 0; i < ne; ++i) q[(size_t)ev[i] * W + eu[i]] = eq[i];
     if (o->edge_u) {

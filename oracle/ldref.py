@@ -35,7 +35,7 @@ class Params(C.Structure):
         ("varpi", C.c_double), ("edge_t", C.c_int32), ("sigma_g", C.c_double),
         ("nu", C.c_int32), ("varsigma", C.c_int32),
         ("n_hyp", C.c_int32), ("max_rounds", C.c_int32),
-        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32),
+        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32), ("vote", C.c_int32),
         ("seed", C.c_uint64),
     ]
 
@@ -93,7 +93,7 @@ def lib():
         L.ldref_votes.argtypes = [_P32, _P32, _P32, _P32, C.c_int, _PD, C.c_int, _P32]
         L.ldref_band.argtypes = [_P32, C.c_int, C.c_int, C.c_int, C.c_int, _P64]
         L.ldref_row_dp.argtypes = [_P64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _P32]
-        L.ldref_weights.argtypes = [_P32, _P32, _P32, _P32, C.c_int, _PD, _PD, C.c_double, C.c_int, _PD]
+        L.ldref_weights.argtypes = [_P32, _P32, _P32, _P32, C.c_int, _PD, _PD, C.c_double, C.c_int, _PD, C.c_int]
         L.ldref_m0m1.argtypes = [_PD, C.c_int, C.c_int, C.c_int, C.c_int, _PD, _PD]
         L.ldref_energy.argtypes = [_PD, _PD, _PD, C.c_int, C.c_int, C.c_int, _PD, _PD, _P32, C.c_int]
         L.ldref_peaks.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_int, _P32, _PD]
@@ -279,13 +279,14 @@ def cand_mask(lane_bits, W: int, v_h: int, v_end: int, vpx, vpy, n_bands=1, dila
     return hit, keep, int(kept)
 
 
-def weights(eu, ev, egx, egy, vpx, vpy, sigma_g=3.5, squared=0):
+def weights(eu, ev, egx, egy, vpx, vpy, sigma_g=3.5, squared=0, vote=0):
+    """q per edge: G_x w_g (vote 0) or the prior work's vote |grad| cos(theta_e - theta_Vp) (vote 1)."""
     eu, ev, egx, egy = [np.ascontiguousarray(a, dtype=np.int32) for a in (eu, ev, egx, egy)]
     vpx = np.ascontiguousarray(vpx, dtype=np.float64)
     vpy = np.ascontiguousarray(vpy, dtype=np.float64)
     q = np.zeros(len(eu))
     lib().ldref_weights(_p32(eu), _p32(ev), _p32(egx), _p32(egy), len(eu), _pd(vpx), _pd(vpy), sigma_g, squared,
-                        _pd(q))
+                        _pd(q), int(vote))
     return q
 
 

@@ -480,6 +480,37 @@ def test_weights_special_angles():
     assert q[1] == 0.0
 
 
+def test_prior_work_vote_against_angles():
+    """vote = 1: V(e) = |grad| cos(theta_e - theta_Vp), theta_e the direction of the tangent
+    (-G_y, G_x), theta_Vp that of the ray from V_p(v) to the pixel, both from arctan2."""
+    rng = np.random.default_rng(5)
+    n = 3000
+    eu = rng.integers(0, 400, n).astype(np.int32)
+    ev = rng.integers(150, 375, n).astype(np.int32)
+    egx = rng.integers(-700, 700, n).astype(np.int32)
+    egy = rng.integers(-700, 700, n).astype(np.int32)
+    vpx = rng.uniform(100, 300, 375)
+    vpy = rng.uniform(100, 140, 375)
+    q = oracle.weights(eu, ev, egx, egy, vpx, vpy, vote=1)
+    th_e = np.arctan2(egx.astype(float), -egy.astype(float))
+    th_p = np.arctan2(ev - vpy[ev], eu - vpx[ev])
+    want = np.hypot(egx, egy) * np.cos(th_e - th_p)
+    assert np.allclose(q, want, rtol=1e-12, atol=1e-9)
+
+
+def test_prior_work_vote_special_cases():
+    vpx = np.array([0.0] * 10 + [50.0])
+    vpy = np.zeros(11)
+    # V_p straight above: a vertical edge votes its G_x (either sign), a horizontal one 0,
+    # a tangent 60 degrees off the ray half its magnitude, the pixel at V_p itself 0
+    q = oracle.weights([50, 50, 50], [10, 10, 10], [7, -7, 0], [0, 0, 5], vpx, vpy, vote=1)
+    assert q[0] == 7.0 and q[1] == -7.0 and q[2] == 0.0
+    g = 1000.0
+    q = oracle.weights([50], [10], [500], [-866], vpx, vpy, vote=1)[0]
+    assert abs(q - 500.0) < 1e-9 and abs(np.hypot(500, 866) - g) < 0.5
+    assert oracle.weights([0], [0], [30], [40], np.zeros(1), np.zeros(1), vote=1)[0] == 0.0
+
+
 # ----------------------------------------------------------------------------- O13 M0/M1
 def test_m0_m1_match_scipy():
     rng = np.random.default_rng(8)
