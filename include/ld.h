@@ -83,6 +83,10 @@ typedef struct ld_params {
     double rho_lpv;        /* lane threshold: E < rho_lpv * min E (not given): 0.25 */
     int32_t d_nms;         /* minimum lane separation in px; 0 -> max(8, width/64) */
     int32_t weight_squared;/* 0: w_g exponent as printed; 1: squared (Gaussian) reading */
+    int32_t vote;          /* 0: q = G_x w_g (Eq. sigma_g); 1: the authors' prior vote named at
+                              the opening of Sec. 2.4, |grad(e)| cos(theta_e - theta_Vp), with
+                              theta_e the tangent (-G_y, G_x) and theta_Vp the ray from V_p(v)
+                              to the pixel (an A/B variant; the rest of the path unchanged) */
     uint64_t seed;         /* Philox key word 0 of the RANSAC samples */
 } ld_params;
 

@@ -1330,12 +1330,15 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
 // write before its reads.  Rows are padded to the NC * 256 columns the threads own (the
 // columns past W hold zeros), so the column loops carry no bounds test.  The row loop is
 // unrolled nine times so that the ring rotates by renaming registers instead of moving them.
+// mode 0 / 1: G_x w_g with the exponent as printed / squared; mode 2: the prior work's vote
+// |grad| cos(theta_e - theta_Vp) = t . (p - V_p) / |p - V_p| = -dot / |r|, in FP64 (no gate)
 __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
     const double tx = (double)(-ed.gy), ty = (double)ed.gx;
     const double rx = vx - (double)ed.u, ry = vy - (double)r;
     const double dot = tx * rx + ty * ry;
     const double tt = tx * tx + ty * ty;
     const double rr = rx * rx + ry * ry;
+    if (sq == 2) return rr > 0.0 ? (float)(-dot / sqrt(rr)) : 0.0f;
     if (!(dot * dot >= (0.75 * tt) * rr)) return 0.0f;
     const double cr = tx * ry - ty * rx;
     const float delta = atan2f((float)fabs(cr), (float)fabs(dot));
@@ -1372,7 +1375,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
     const double* tB = tf + 5 * H;
     const int v_h = fi.v_h, v_end = fi.v_end;
     const float inv_sg2 = (float)(1.0 / (d.P.sigma_g * d.P.sigma_g));
-    const int sq = d.P.weight_squared;
+    const int sq = d.P.vote ? 2 : d.P.weight_squared;
     const ld_edge* edges = d.edges + (int64_t)b * H * W;
     float* qbuf = d.qbuf + (int64_t)b * H * W;
     const int32_t* rowcnt = d.rowcnt + (int64_t)b * H;
@@ -2342,7 +2345,8 @@ ld_status check_params(const ld_params& p) {
     if (p.eps_num < 0 || p.eps_den < 1 || p.edge_t < 0 || p.edge_t > 46340) return LD_E_INVAL;
     if (p.nu != 1 || p.varsigma != 3) return LD_E_INVAL;    // the kernels are built for the paper's box
     if (!(p.sigma_g > 0.0) || !(p.tr_x >= 0.0) || !(p.tr_y >= 0.0) || !(p.varpi >= 0.0)) return LD_E_INVAL;
-    if (p.d_nms < 0) return LD_E_INVAL;
+    if (p.d_nms < 0 || (p.weight_squared != 0 && p.weight_squared != 1) || (p.vote != 0 && p.vote != 1))
+        return LD_E_INVAL;
     return LD_OK;
 }
 
@@ -2591,7 +2595,7 @@ void ld_params_default(ld_params* p) {
     p->chi = 25; p->tau_y_max = 6; p->tau_x_max = 5; p->lambda_y = 1; p->lambda_x = 1;
     p->tr_y = 4.0; p->tr_x = 16.0; p->eps_num = 99; p->eps_den = 100; p->varpi = 3.0;
     p->edge_t = 100; p->sigma_g = 3.5; p->nu = 1; p->varsigma = 3; p->n_hyp = 64; p->max_rounds = 16;
-    p->rho_lpv = 0.25; p->d_nms = 0; p->weight_squared = 0; p->seed = 0;
+    p->rho_lpv = 0.25; p->d_nms = 0; p->weight_squared = 0; p->vote = 0; p->seed = 0;
 }
 
 const char* ld_status_string(ld_status s) {

@@ -36,7 +36,7 @@ class ld_params(C.Structure):
         ("varpi", C.c_double), ("edge_t", C.c_int32), ("sigma_g", C.c_double),
         ("nu", C.c_int32), ("varsigma", C.c_int32),
         ("n_hyp", C.c_int32), ("max_rounds", C.c_int32),
-        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32),
+        ("rho_lpv", C.c_double), ("d_nms", C.c_int32), ("weight_squared", C.c_int32), ("vote", C.c_int32),
         ("seed", C.c_uint64),
     ]
 

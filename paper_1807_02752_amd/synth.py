@@ -41,6 +41,8 @@ class Scene:
     lanes: list            # list of (s_k, dashed)
     gain: float = 1.0
     obstacles: list = field(default_factory=list)   # (u0, u1, v_top, v_base, disparity)
+    lane_values: list | None = None                 # per-lane marking grey (None: one value for all)
+    paint: list = field(default_factory=list)       # road paint: (v_top, v_bottom, u_left, u_right, slope)
 
     def f(self, v):
         w = np.asarray(v, dtype=np.float64) - self.v0
@@ -100,10 +102,27 @@ def _render(scene: Scene, rng: np.random.Generator, *, disp_noise: float, dropou
     v = np.arange(H, dtype=np.float64)[:, None]
     if width_fn is None:
         width_fn = lambda d: np.full_like(d, 3.0)   # noqa: E731  (constant 3 px markings)
-    cov = np.zeros((H, W))
-    for k in range(len(scene.lanes)):
-        _lane_coverage(scene, k, width_fn, dash_k, cov)
-    grey = road_value + cov * (lane_value - road_value) + rng.normal(0.0, noise, size=(H, W))
+    if scene.lane_values is None:
+        cov = np.zeros((H, W))
+        for k in range(len(scene.lanes)):
+            _lane_coverage(scene, k, width_fn, dash_k, cov)
+        grey = road_value + cov * (lane_value - road_value) + rng.normal(0.0, noise, size=(H, W))
+    else:
+        grey = np.full((H, W), road_value)
+        for k in range(len(scene.lanes)):
+            cov = np.zeros((H, W))
+            _lane_coverage(scene, k, width_fn, dash_k, cov)
+            grey += cov * (scene.lane_values[k] - road_value)
+        grey += rng.normal(0.0, noise, size=(H, W))
+    # road paint other than lane markings: bright parallelograms on the road surface (rows
+    # v_top..v_bottom, columns u_left + slope (v_bottom - v) .. u_right + slope (v_bottom - v))
+    for (vt, vb, ul, ur, sl) in scene.paint:
+        for vv in range(max(0, vt), min(H - 1, vb) + 1):
+            sh = sl * (vb - vv)
+            c0, c1 = int(round(ul + sh)), int(round(ur + sh))
+            c0, c1 = max(0, c0), min(W - 1, c1)
+            if c0 <= c1:
+                grey[vv, c0:c1 + 1] = lane_value + rng.normal(0.0, noise, size=c1 - c0 + 1)
     fv = scene.f(v)                                       # H x 1
     below = (v >= scene.v0)
     # disparity of the road surface, zero (invalid) above the horizon
@@ -247,6 +266,49 @@ def make_c2(seed: int = 0, idx: int = 0):
     return grey, disp, sc
 
 
+def _paint(scene: Scene, rng: np.random.Generator, n: int):
+    """Road paint between the two inner lanes: bars across the lane (stop lines, whose edges
+    run along the rows) and strokes slanted 45 degrees (arrow heads), each about 0.4 m deep,
+    on road rows in the lower two thirds of the road."""
+    H = scene.height
+    out = []
+    v_lo = scene.v0 + (H - 1 - scene.v0) / 3.0
+    for i in range(n):
+        vb = int(rng.uniform(v_lo, H - 1))
+        d = float(scene.f(vb))
+        depth = max(2, int(round(0.05 * d)))          # rows a 0.4 m deep patch covers, roughly
+        ul = float(scene.lane_u(1, vb)) + 0.25 * d
+        ur = float(scene.lane_u(2, vb)) - 0.25 * d
+        if ur - ul < 8:
+            continue
+        if i % 2 == 0:
+            out.append((vb - depth + 1, vb, ul, ur, 0.0))
+        else:
+            w = max(3.0, 0.28 * d)
+            mid = 0.5 * (ul + ur)
+            ln = int(round(min(0.5 * (ur - ul), 3 * d)))
+            out.append((vb - ln + 1, vb, mid - w, mid + w, 1.0 if rng.random() < 0.5 else -1.0))
+    return out
+
+
+def make_hard(kind: str, seed: int = 0, idx: int = 0):
+    """Hard cases on the 1242x375 sequences: 'low_contrast' renders the left inner lane at
+    road + 35 grey levels and the outer lanes at road + 30 (the right inner lane at 200);
+    'markings' adds road paint between the inner lanes (bars across the lane and 45-degree
+    strokes, six per frame).  Otherwise as make_c2."""
+    sc = scene_c2(seed, idx)
+    rng = _rng(seed ^ 0x5A5A, idx)
+    sc.obstacles = _obstacles(sc, rng, 0.10)
+    if kind == "low_contrast":
+        sc.lane_values = [120.0, 125.0, 200.0, 120.0]
+    elif kind == "markings":
+        sc.paint = _paint(sc, rng, 6)
+    else:
+        raise ValueError(kind)
+    grey, disp = _render(sc, rng, disp_noise=0.2, dropout=0.0, dash_k=None, width_fn=marking_width)
+    return grey, disp, sc
+
+
 def scene_c3(seed: int, idx: int) -> Scene:
     rng = _rng(seed, 1 << 41)
     q = rng.uniform(-6e-5, 6e-5)
@@ -278,6 +340,8 @@ def make_frame(config: str, seed: int = 0, idx: int = 0):
         return make_c2(seed, idx)
     if config == "c3":
         return make_c3(seed, idx)
+    if config in ("low_contrast", "markings"):
+        return make_hard(config, seed, idx)
     raise ValueError(config)
 
 

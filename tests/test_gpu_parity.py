@@ -221,6 +221,18 @@ def test_dp_windows_and_weights(tau_y, lam_y, tau_x, lam_x):
     compare_frame(out, 0, g, d, 128, params=pr)
 
 
+@pytest.mark.parametrize("kind,vote", [("c2", 1), ("low_contrast", 0), ("low_contrast", 1), ("markings", 0),
+                                       ("markings", 1)])
+def test_prior_work_vote_and_hard_cases(kind, vote):
+    # the prior work's edge vote in place of G_x w_g (vote = 1), and the hard-case frames (a
+    # faint lane, road paint between the lanes) on both weightings: every step as the oracle's
+    greys, disps, _ = synth.make_batch(kind, 2, 2, 9)
+    pg, pr = _ld().params_default(vote=vote), oracle.default_params(vote=vote)
+    out = run_gpu(greys, disps, 128, params=pg)
+    for b in range(2):
+        compare_frame(out, b, greys[b], disps[b], 128, params=pr)
+
+
 @pytest.mark.parametrize("kind", ["all_invalid", "obstacle_only", "flat_image", "random"])
 def test_degenerate_frames(kind):
     g, d = synth.degenerate(kind)
