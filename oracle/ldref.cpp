@@ -445,6 +445,84 @@ int ldref_sobel(const uint8_t* grey, int64_t pitch, int W, int H, int32_t* gx, i
 }
 
 // ------------------------------------------------------------------------------------
+// Lane tracking across frames.  The paper names a tracking algorithm as future work (Sec. 4)
+// without defining one; this is the reading taken (T1..T5).  T1: a track is a lane's start
+// column x on row v_max with a rate dx in columns per frame; a frame first predicts every
+// track, x_hat = x + dx.  T2: a frame without a road or a vanishing point has no detections.
+// T3: detections are assigned to predicted tracks greedily, the closest pair |u - x_hat| first
+// (ties to the lower track slot, then the lower detection index), only pairs within `gate`.
+// T4: an alpha-beta filter updates a matched track, r = u - x_hat, x = x_hat + alpha r,
+// dx = dx + beta r, hits + 1, misses = 0; an unmatched track keeps x = x_hat and counts a miss,
+// and is dropped once misses > max_misses (the others keep their order).  T5: unmatched
+// detections, in their order, start tracks (x = u, dx = 0, hits = 1) with consecutive ids
+// while fewer than 16 tracks live.  A track with hits >= confirm is reported.  FP64, in the
+// order written.
+struct ldref_track {
+    int32_t n, next_id;
+    int64_t frames;
+    int32_t id[16], hits[16], misses[16];
+    double x[16], dx[16];
+};
+
+int ldref_track_update(ldref_track* s, const int32_t* u, int n_det, int valid, double alpha, double beta,
+                       double gate, int max_misses) {
+    if (!valid) n_det = 0;
+    if (n_det > 16) n_det = 16;
+    double xh[16];
+    for (int t = 0; t < s->n; ++t) xh[t] = s->x[t] + s->dx[t];
+    int match_t[16], match_d[16];
+    for (int t = 0; t < 16; ++t) match_t[t] = -1;
+    for (int d = 0; d < 16; ++d) match_d[d] = -1;
+    for (;;) {
+        int bt = -1, bd = -1;
+        double best = 0.0;
+        for (int t = 0; t < s->n; ++t) {
+            if (match_t[t] >= 0) continue;
+            for (int d = 0; d < n_det; ++d) {
+                if (match_d[d] >= 0) continue;
+                const double dist = std::fabs((double)u[d] - xh[t]);
+                if (!(dist <= gate)) continue;
+                if (bt < 0 || dist < best) { bt = t; bd = d; best = dist; }
+            }
+        }
+        if (bt < 0) break;
+        match_t[bt] = bd;
+        match_d[bd] = bt;
+    }
+    for (int t = 0; t < s->n; ++t) {
+        if (match_t[t] >= 0) {
+            const double r = (double)u[match_t[t]] - xh[t];
+            s->x[t] = xh[t] + alpha * r;
+            s->dx[t] = s->dx[t] + beta * r;
+            s->hits[t] += 1;
+            s->misses[t] = 0;
+        } else {
+            s->x[t] = xh[t];
+            s->misses[t] += 1;
+        }
+    }
+    int k = 0;
+    for (int t = 0; t < s->n; ++t) {
+        if (s->misses[t] > max_misses) continue;
+        s->id[k] = s->id[t]; s->hits[k] = s->hits[t]; s->misses[k] = s->misses[t];
+        s->x[k] = s->x[t]; s->dx[k] = s->dx[t];
+        ++k;
+    }
+    s->n = k;
+    for (int d = 0; d < n_det; ++d) {
+        if (match_d[d] >= 0 || s->n >= 16) continue;
+        const int t = s->n++;
+        s->id[t] = s->next_id++;
+        s->hits[t] = 1;
+        s->misses[t] = 0;
+        s->x[t] = (double)u[d];
+        s->dx[t] = 0.0;
+    }
+    s->frames += 1;
+    return s->n;
+}
+
+// ------------------------------------------------------------------------------------
 // Bilateral pre-filter (Sec. 2.3.1, Eq. bilateral_filter and the two weights defined after
 // it): I_bf(u, v) = sum w_s w_r I / sum w_s w_r over the (2 rho + 1) x (2 rho + 1) window
 // centred at (u, v), w_s = exp(-((i-u)^2 + (j-v)^2) / sigma_s^2) on the offset and

@@ -85,6 +85,8 @@ def lib():
                                    C.c_uint64, C.c_uint64, C.c_int64, C.c_int, _PD, C.POINTER(FitOut), _P32]
         L.ldref_road_tables.argtypes = [C.POINTER(FitOut), C.c_int, _PD, _PD, _PD, _P32]
         L.ldref_sobel.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P32, _P32]
+        L.ldref_track_update.argtypes = [C.POINTER(TrackState), _P32, C.c_int, C.c_int, C.c_double, C.c_double,
+                                         C.c_double, C.c_int]
         L.ldref_bilateral.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
                                       C.c_int, C.c_void_p, C.c_int64, _PF]
         L.ldref_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, _P32]
@@ -341,6 +343,27 @@ def sobel(grey: np.ndarray):
     gy = np.zeros((H, W), np.int32)
     lib().ldref_sobel(grey.ctypes.data, grey.strides[0], W, H, _p32(gx), _p32(gy))
     return gx, gy
+
+
+class TrackState(C.Structure):
+    """Tracker state of one stream (zero-filled: no tracks)."""
+    _fields_ = [("n", C.c_int32), ("next_id", C.c_int32), ("frames", C.c_int64),
+                ("id", C.c_int32 * 16), ("hits", C.c_int32 * 16), ("misses", C.c_int32 * 16),
+                ("x", C.c_double * 16), ("dx", C.c_double * 16)]
+
+    def tracks(self, confirm: int = 1):
+        """[(id, x, dx, hits, misses)] of the tracks with hits >= confirm, in slot order."""
+        return [(self.id[t], self.x[t], self.dx[t], self.hits[t], self.misses[t]) for t in range(self.n)
+                if self.hits[t] >= confirm]
+
+
+def track_update(state: TrackState, u_start, valid: bool = True, alpha: float = 0.5, beta: float = 0.1,
+                 gate: float = 24.0, max_misses: int = 5) -> TrackState:
+    """Fold one frame's lane start columns into a stream's tracks (in place)."""
+    u = np.ascontiguousarray(np.asarray(u_start, dtype=np.int32)[:16])
+    lib().ldref_track_update(C.byref(state), _p32(u) if len(u) else None, len(u), 1 if valid else 0,
+                             alpha, beta, gate, max_misses)
+    return state
 
 
 def bilateral(grey: np.ndarray, rho: int = 5, sigma_s: float = 300.0, sigma_r: float = 0.3, row0: int = 0):
