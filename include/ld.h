@@ -190,6 +190,48 @@ ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const v
 ld_status ld_bilateral(ld_frame f, const uint8_t* grey, int64_t grey_pitch, uint8_t* out, int64_t out_pitch,
                        int32_t rho, float sigma_s, float sigma_r, int32_t road_rows, void* hip_stream);
 
+/* Lane tracking across frames.  The paper names a tracking algorithm as future work (Sec. 4)
+ * and defines none; this one filters each lane's start column on row v_max:
+ *  - predict every track, x_hat = x + dx;
+ *  - a frame flagged LD_FLAG_NOROAD or LD_FLAG_NOVP has no detections;
+ *  - assign detections (ld_lanes.u_start) to predicted tracks greedily, the closest pair
+ *    |u - x_hat| first (ties: lower track slot, then lower lane index), pairs within `gate`;
+ *  - matched: r = u - x_hat, x = x_hat + alpha r, dx = dx + beta r, hits + 1, misses = 0;
+ *    unmatched: x = x_hat, misses + 1, dropped once misses > max_misses (the rest keep order);
+ *  - unmatched detections start tracks (x = u, dx = 0, hits = 1, id = next_id++) while fewer
+ *    than LD_MAX_LANES tracks live.
+ * FP64 in the order written.  A track with hits >= confirm is a confirmed lane. */
+typedef struct ld_track_state {
+    int32_t n;                        /* live tracks, in slot order */
+    int32_t next_id;                  /* id the next new track gets */
+    int64_t frames;                   /* frames folded in */
+    int32_t id[LD_MAX_LANES];
+    int32_t hits[LD_MAX_LANES];       /* frames with a detection since the track's birth */
+    int32_t misses[LD_MAX_LANES];     /* consecutive frames without one */
+    double x[LD_MAX_LANES];           /* filtered start column on row v_max */
+    double dx[LD_MAX_LANES];          /* filtered rate, columns per frame */
+} ld_track_state;                     /* all zero: a stream without tracks */
+
+typedef struct ld_track_params {
+    double alpha;                     /* (0, 1]  (0.5) */
+    double beta;                      /* [0, 1]  (0.1) */
+    double gate;                      /* > 0, columns (24) */
+    int32_t confirm;                  /* >= 1 (3): hits that confirm a track */
+    int32_t max_misses;               /* >= 0 (5) */
+} ld_track_params;
+
+void ld_track_params_default(ld_track_params* tp);
+
+/* Fold the lanes of the active frames of f into their streams' tracker states, one frame per
+ * state: frame b updates states[state_index[b]] (state_index: nullable device int32 per
+ * frame, identity when NULL).  The indices of one call must be distinct (frames of one stream
+ * go to successive calls, in frame order); a negative index skips the frame.
+ *  lanes  : device ld_lanes per frame (from ld_peaks / ld_detect / ld_detect_pruned).
+ *  states : device ld_track_state array, updated in place.
+ * LD_E_INVAL for NULL pointers or parameters out of range. */
+ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const int32_t* state_index,
+                   const ld_track_params* tp, void* hip_stream);
+
 /* Scratch of ld_detect_noalloc, per GPU (64 MiB). */
 #define LD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 

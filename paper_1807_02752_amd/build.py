@@ -25,7 +25,8 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp,
            os.path.join(CSRC, "ld.hip"), os.path.join(CSRC, "ld_server.hip"),
-           os.path.join(CSRC, "ld_cnn.hip"), os.path.join(CSRC, "ld_filter.hip")]
+           os.path.join(CSRC, "ld_cnn.hip"), os.path.join(CSRC, "ld_filter.hip"),
+           os.path.join(CSRC, "ld_track.hip")]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

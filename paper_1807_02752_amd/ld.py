@@ -136,6 +136,10 @@ def lib():
         L.ld_detect_noalloc.restype = i32
         L.ld_bilateral.argtypes = [vp, vp, i64, vp, i64, i32, C.c_float, C.c_float, i32, vp]
         L.ld_bilateral.restype = i32
+        L.ld_track_params_default.argtypes = [C.POINTER(ld_track_params)]
+        L.ld_track_params_default.restype = None
+        L.ld_track.argtypes = [vp, vp, vp, vp, C.POINTER(ld_track_params), vp]
+        L.ld_track.restype = i32
         for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
                      "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"):
             getattr(L, name).restype = i32
@@ -153,7 +157,7 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
             "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc",
-            "ld_cnn_save", "ld_cnn_load", "ld_bilateral"]
+            "ld_cnn_save", "ld_cnn_load", "ld_bilateral", "ld_track_params_default", "ld_track"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -222,6 +226,30 @@ def ld_detect_noalloc(width, height, batch, fmt, d_max, params, grey, grey_pitch
 
 
 LD_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+class ld_track_params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("gate", C.c_double), ("confirm", C.c_int32),
+                ("max_misses", C.c_int32)]
+
+
+# ld_track_state as a numpy record (device arrays of it are uint8 tensors of TRACK_STATE_BYTES each)
+TRACK_DTYPE = np.dtype([("n", np.int32), ("next_id", np.int32), ("frames", np.int64), ("id", np.int32, 16),
+                        ("hits", np.int32, 16), ("misses", np.int32, 16), ("x", np.float64, 16),
+                        ("dx", np.float64, 16)], align=True)
+TRACK_STATE_BYTES = TRACK_DTYPE.itemsize
+
+
+def track_params_default(**overrides) -> ld_track_params:
+    tp = ld_track_params()
+    lib().ld_track_params_default(C.byref(tp))
+    for k, v in overrides.items():
+        setattr(tp, k, v)
+    return tp
+
+
+def ld_track(f, lanes, states, state_index, tp, stream):
+    return lib().ld_track(f, lanes, states, state_index, C.byref(tp) if tp is not None else None, stream)
 
 
 def ld_bilateral(f, grey, grey_pitch, out, out_pitch, rho, sigma_s, sigma_r, road_rows, stream):
@@ -493,6 +521,21 @@ class Detector:
         """Bilateral pre-filter of the grey images into `out` (uint8, same shape)."""
         check(ld_bilateral(self.handle, _ptr(grey), self._pitch(grey), _ptr(out), self._pitch(out), int(rho),
                            float(sigma_s), float(sigma_r), 1 if road_rows else 0, _stream()), "ld_bilateral")
+
+    def track(self, lanes, states, state_index=None, params: ld_track_params | None = None):
+        """Fold the lanes of the active frames into device tracker states (uint8 tensor of
+        n x TRACK_STATE_BYTES; frame b -> state_index[b], identity when None)."""
+        check(ld_track(self.handle, _ptr(lanes), _ptr(states), _ptr(state_index), params, _stream()), "ld_track")
+
+    @staticmethod
+    def track_states(n: int):
+        """Zeroed device tracker states for n streams."""
+        import torch
+        return torch.zeros((n, TRACK_STATE_BYTES), dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def parse_track_states(states) -> np.ndarray:
+        return np.frombuffer(states.cpu().numpy().tobytes(), dtype=TRACK_DTYPE)
 
     def sync(self):
         check(ld_sync(self.handle), "ld_sync")
