@@ -471,6 +471,9 @@ typedef struct ld_server_config {
     int32_t use_graphs;                     /* 1: replay a captured graph per engine */
     int32_t seed_from_state;                /* 1: seed V_px RANSAC with the stream's last fit (also in
                                                the pruned path, for frames without a seed line) */
+    int32_t track;                          /* 1: fold every frame's lanes into its stream's tracker
+                                               state (ld_track, default parameters); read it with
+                                               ld_server_tracks */
     int64_t hbm_budget;                     /* bytes of device memory the engines may use */
     ld_cnn cnn;                             /* nullable: run ld_detect_pruned with this network
                                                (plain fallback per frame); read only, must
@@ -505,6 +508,12 @@ ld_status ld_server_poll(ld_server s, ld_server_result* results, int32_t max_res
 ld_status ld_server_pending(ld_server s, int32_t* queued, int32_t* inflight);
 /* Engines created per class and the device bytes they hold. */
 ld_status ld_server_engines(ld_server s, int32_t* per_class /* LD_MAX_CLASSES */, int64_t* bytes);
+
+/* Tracker state of one stream (config track = 1; LD_E_STATE otherwise), copied to host memory
+ * `out` once the batches in flight have finished: it holds every frame of the stream that has
+ * reached a batch (the server keeps at most one frame per stream in flight, so a stream's
+ * frames are folded in order).  Blocks the calling thread. */
+ld_status ld_server_tracks(ld_server s, int32_t stream_id, ld_track_state* out);
 
 #ifdef __cplusplus
 }

@@ -54,3 +54,8 @@ __host__ __device__ inline int ldi_band_top(int v_h, int H, int n_bands, int k) 
 ld_status ldi_cnn_bits(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t gp, const void* disp, int64_t dp,
                        float* prob_out, int sparse, hipStream_t st);
 const ld_cnn_config* ldi_cnn_config(ld_cnn n);
+
+// ld_track for the serving layer: frame b updates states[stream_ids[b]] with the default
+// tracker parameters (stream ids < the state count, distinct within the launch).
+ld_status ldi_track_streams(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const uint64_t* stream_ids,
+                            hipStream_t st);

@@ -96,6 +96,7 @@ struct ld_server_s {
     std::deque<Request> queue[LD_MAX_CLASSES];
     std::deque<ld_server_result> finished;
     StreamState* d_state = nullptr;
+    ld_track_state* d_tracks = nullptr;   // per stream, with config track
     std::vector<int64_t> next_frame;
     std::vector<int32_t> stream_cls;
     std::vector<uint8_t> in_flight;
@@ -175,7 +176,9 @@ ld_status enqueue_batch_body(ld_server s, Engine* e) {
     }
     if (r != LD_OK) return r;
     hipLaunchKernelGGL(k_store_state, dim3((B + 63) / 64), dim3(64), 0, e->st, s->d_state, e->d_sid, e->d_nact, ldi_frame_fits(e->f));
-    return hipGetLastError() == hipSuccess ? LD_OK : LD_E_HIP;
+    if (hipGetLastError() != hipSuccess) return LD_E_HIP;
+    if (s->d_tracks) return ldi_track_streams(e->f, e->d_lanes, s->d_tracks, e->d_sid, e->st);
+    return LD_OK;
 }
 
 ld_status make_engine(ld_server s, int k, Engine** out) {
@@ -270,7 +273,7 @@ ld_status ld_server_create(const ld_server_config* cfg, const ld_params* p, ld_s
     *out = nullptr;
     const ld_server_config& c = *cfg;
     if (c.n_classes < 1 || c.n_classes > LD_MAX_CLASSES || c.n_streams < 1 || c.n_streams > (1 << 20) ||
-        c.inflight < 1 || c.inflight > 8 || c.max_queue < 1 || c.hbm_budget < 0)
+        c.inflight < 1 || c.inflight > 8 || c.max_queue < 1 || c.hbm_budget < 0 || (c.track != 0 && c.track != 1))
         return LD_E_INVAL;
     for (int k = 0; k < c.n_classes; ++k) {
         if (c.width[k] < 8 || c.width[k] > 4096 || c.height[k] < 8 || c.height[k] > 4096 || c.fmt[k] < 0 ||
@@ -291,7 +294,22 @@ ld_status ld_server_create(const ld_server_config* cfg, const ld_params* p, ld_s
         return LD_E_NOMEM;
     }
     hipLaunchKernelGGL(k_init_state, dim3((c.n_streams + 255) / 256), dim3(256), 0, nullptr, s->d_state, c.n_streams);
-    if (hipDeviceSynchronize() != hipSuccess) { (void)hipFree(s->d_state); delete s; return LD_E_HIP; }
+    if (c.track) {
+        const size_t tb = sizeof(ld_track_state) * (size_t)c.n_streams;
+        if (hipMalloc(&s->d_tracks, tb) != hipSuccess || hipMemset(s->d_tracks, 0, tb) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(s->d_tracks);
+            (void)hipFree(s->d_state);
+            delete s;
+            return LD_E_NOMEM;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(s->d_tracks);
+        (void)hipFree(s->d_state);
+        delete s;
+        return LD_E_HIP;
+    }
     // engines: round-robin over the classes while the budget allows
     bool grew = true;
     for (int round = 0; round < c.inflight && grew; ++round) {
@@ -317,6 +335,7 @@ ld_status ld_server_destroy(ld_server s) {
     if (!s) return LD_OK;
     for (Engine* e : s->engines) free_engine(e);
     (void)hipFree(s->d_state);
+    (void)hipFree(s->d_tracks);
     delete s;
     return LD_OK;
 }
@@ -428,6 +447,16 @@ ld_status ld_server_pending(ld_server s, int32_t* queued, int32_t* inflight) {
     if (queued) *queued = q;
     if (inflight) *inflight = f;
     return LD_OK;
+}
+
+ld_status ld_server_tracks(ld_server s, int32_t stream_id, ld_track_state* out) {
+    if (!s || !out || stream_id < 0 || stream_id >= s->cfg.n_streams) return LD_E_INVAL;
+    if (!s->d_tracks) return LD_E_STATE;
+    // the engines' streams are non-blocking: wait for the batches in flight first
+    for (Engine* e : s->engines)
+        if (hipStreamSynchronize(e->st) != hipSuccess) return LD_E_HIP;
+    return hipMemcpy(out, s->d_tracks + stream_id, sizeof(ld_track_state), hipMemcpyDeviceToHost) == hipSuccess
+               ? LD_OK : LD_E_HIP;
 }
 
 ld_status ld_server_engines(ld_server s, int32_t* per_class, int64_t* bytes) {

@@ -18,13 +18,14 @@ namespace {
 constexpr int kT = 64;
 static_assert(sizeof(ld_track_state) == 464 && offsetof(ld_track_state, x) == 208, "ld_track_state layout");
 
+template <typename Index>
 __global__ __launch_bounds__(kT) void k_track(int nframes, const int32_t* nact, const ld_lanes* lanes,
-                                              ld_track_state* states, const int32_t* state_index,
+                                              ld_track_state* states, const Index* state_index,
                                               ld_track_params P) {
     const int b = blockIdx.x * kT + threadIdx.x;
     const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
     if (b >= nf) return;
-    const int si = state_index != nullptr ? state_index[b] : b;
+    const int64_t si = state_index != nullptr ? (int64_t)state_index[b] : b;
     if (si < 0) return;
     ld_track_state* s = states + si;
     const ld_lanes& L = lanes[b];
@@ -114,8 +115,20 @@ extern "C" ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state*
         return LD_E_INVAL;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (V.active > 0)
-        hipLaunchKernelGGL(k_track, dim3((V.active + kT - 1) / kT), dim3(kT), 0, st, V.active, V.nact, lanes, states,
-                           state_index, P);
+        hipLaunchKernelGGL(k_track<int32_t>, dim3((V.active + kT - 1) / kT), dim3(kT), 0, st, V.active, V.nact, lanes,
+                           states, state_index, P);
     if (hipGetLastError() != hipSuccess) return LD_E_HIP;
     return ldi_frame_set_last(f, hip_stream);
+}
+
+ld_status ldi_track_streams(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const uint64_t* stream_ids,
+                            hipStream_t st) {
+    ldi_frame_view V;
+    if (!f || !lanes || !states || !stream_ids || ldi_frame_get_view(f, &V) != LD_OK) return LD_E_INVAL;
+    ld_track_params P;
+    ld_track_params_default(&P);
+    if (V.active > 0)
+        hipLaunchKernelGGL(k_track<uint64_t>, dim3((V.active + kT - 1) / kT), dim3(kT), 0, st, V.active, V.nact, lanes,
+                           states, stream_ids, P);
+    return hipGetLastError() == hipSuccess ? LD_OK : LD_E_HIP;
 }

@@ -63,7 +63,7 @@ class ld_server_config(C.Structure):
                 ("fmt", C.c_int32 * LD_MAX_CLASSES), ("d_max", C.c_int32 * LD_MAX_CLASSES),
                 ("max_batch", C.c_int32 * LD_MAX_CLASSES), ("n_streams", C.c_int32), ("inflight", C.c_int32),
                 ("max_queue", C.c_int32), ("use_graphs", C.c_int32), ("seed_from_state", C.c_int32),
-                ("hbm_budget", C.c_int64), ("cnn", C.c_void_p)]
+                ("track", C.c_int32), ("hbm_budget", C.c_int64), ("cnn", C.c_void_p)]
 
 
 class ld_server_result(C.Structure):
@@ -140,6 +140,8 @@ def lib():
         L.ld_track_params_default.restype = None
         L.ld_track.argtypes = [vp, vp, vp, vp, C.POINTER(ld_track_params), vp]
         L.ld_track.restype = i32
+        L.ld_server_tracks.argtypes = [vp, i32, vp]
+        L.ld_server_tracks.restype = i32
         for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
                      "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned"):
             getattr(L, name).restype = i32
@@ -157,7 +159,8 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_server_submit", "ld_server_poll", "ld_server_pending", "ld_server_engines",
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
             "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc",
-            "ld_cnn_save", "ld_cnn_load", "ld_bilateral", "ld_track_params_default", "ld_track"]
+            "ld_cnn_save", "ld_cnn_load", "ld_bilateral", "ld_track_params_default", "ld_track",
+            "ld_server_tracks"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -387,7 +390,7 @@ def cnn_config(**overrides) -> ld_cnn_config:
 
 
 def server_config(classes, *, n_streams=32, inflight=2, max_queue=256, use_graphs=True, seed_from_state=True,
-                  hbm_budget=64 << 30, cnn=None):
+                  hbm_budget=64 << 30, cnn=None, track=False):
     """classes: list of (width, height, fmt, d_max, max_batch).  cnn: a Cnn whose network runs
     the pruned path (it must stay open while the server lives)."""
     cfg = ld_server_config()
@@ -397,6 +400,7 @@ def server_config(classes, *, n_streams=32, inflight=2, max_queue=256, use_graph
         cfg.width[k], cfg.height[k], cfg.fmt[k], cfg.d_max[k], cfg.max_batch[k] = w, h, f, dm, mb
     cfg.n_streams, cfg.inflight, cfg.max_queue = n_streams, inflight, max_queue
     cfg.use_graphs, cfg.seed_from_state, cfg.hbm_budget = int(use_graphs), int(seed_from_state), int(hbm_budget)
+    cfg.track = int(track)
     return cfg
 
 
@@ -439,6 +443,12 @@ class Server:
                         "t_submit": r.t_submit, "t_done": r.t_done, "n": L.n, "flags": L.flags, "v_h": L.v_h,
                         "v_end": L.v_end, "u_start": list(L.u_start[: L.n]), "energy": list(L.energy[: L.n])})
         return out
+
+    def tracks(self, stream_id: int) -> np.ndarray:
+        """The stream's tracker state (config track=True) as a TRACK_DTYPE record."""
+        buf = np.zeros(1, dtype=TRACK_DTYPE)
+        check(lib().ld_server_tracks(self.handle, int(stream_id), buf.ctypes.data_as(C.c_void_p)), "ld_server_tracks")
+        return buf[0]
 
     def pending(self):
         st, q, f = ld_server_pending(self.handle)

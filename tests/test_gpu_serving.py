@@ -220,3 +220,46 @@ def test_server_admission_by_budget_and_queue():
                                       hbm_budget=min(sizes) + 1024))
     assert tiny.submit(0, 1, *frames[1])[0] == ld.LD_E_NOMEM     # its engine can never fit
     tiny.close()
+
+
+def test_server_tracks_follow_each_stream():
+    """With tracking on, each stream's device tracker state (graph replays, mixed classes,
+    interleaved arrivals) equals the oracle's tracker fed that stream's served lanes in frame
+    order."""
+    ld = _ld()
+    frames = _frames(6, 8)
+    rng = np.random.default_rng(5)
+    order = [s for s in rng.permutation(np.repeat(np.arange(6), 8))]
+    cfg = ld.server_config(CLASSES, n_streams=6, inflight=2, max_queue=64, use_graphs=True, track=True)
+    srv = ld.Server(cfg)
+    keep, got, pos = [], {s: {} for s in frames}, {s: 0 for s in frames}
+    for s in order:
+        g, d, cls = frames[s][pos[s]]
+        gt, dt = torch.from_numpy(g).cuda(), torch.from_numpy(d).cuda()
+        keep.append((gt, dt))
+        assert srv.submit(int(s), cls, gt, dt)[0] == ld.LD_OK
+        pos[s] += 1
+        for r in srv.poll():
+            got[r["stream"]][r["frame_idx"]] = r
+    for _ in range(100000):
+        q, f = srv.pending()
+        for r in srv.poll():
+            got[r["stream"]][r["frame_idx"]] = r
+        if q == 0 and f == 0:
+            break
+    for s in frames:
+        ref = oracle.TrackState()
+        for k in range(len(frames[s])):
+            r = got[s][k]
+            oracle.track_update(ref, sorted(r["u_start"]), valid=not (r["flags"] & 3))
+        st = srv.tracks(s)
+        assert st["n"] == ref.n and st["frames"] == len(frames[s]) == ref.frames
+        assert list(st["id"][: ref.n]) == list(ref.id[: ref.n])
+        assert np.array_equal(st["x"][: ref.n], np.array(ref.x[: ref.n]))
+        assert np.array_equal(st["dx"][: ref.n], np.array(ref.dx[: ref.n]))
+    off = ld.Server(ld.server_config(CLASSES[:1], n_streams=2))
+    buf = np.zeros(1, dtype=ld.TRACK_DTYPE)
+    import ctypes as C
+    assert ld.lib().ld_server_tracks(off.handle, 0, buf.ctypes.data_as(C.c_void_p)) == ld.LD_E_STATE
+    off.close()
+    srv.close()
