@@ -445,6 +445,152 @@ int ldref_sobel(const uint8_t* grey, int64_t pitch, int W, int H, int32_t* gx, i
 }
 
 // ------------------------------------------------------------------------------------
+// Stereo disparity (Sec. 2.1): NCC block matching with the block statistics memorised from
+// integral images (Alg. "integral image initialisation", Eq. integral_image, Eq. sigma_l_1,
+// Eq. sigma_r_1, Eq. ncc_1), search range propagation row by row from the bottom (Eq. srp,
+// Alg. "SRP-based disparity map estimation") and the left-right consistency check (Alg. "LRC
+// check").  Readings (D1..D6):
+// D1: block side 2 rho + 1, n = (2 rho + 1)^2; a pixel is matched only when its block lies in
+//     the image (rho <= u <= W-1-rho, rho <= v <= H-1-rho), others get 0.  Disparity 0 marks
+//     "no match" (the value the check writes), so the search range is 1..d_max.
+// D2: with S = block sum, Q = block sum of squares (from the integral images) and
+//     P = sum of I_l(i,j) I_r(i-d,j), the cost of Eq. ncc_1 equals
+//     c = (n P - S_l S_r) / (sqrt(n Q_l - S_l^2) sqrt(n Q_r - S_r^2)); the integers are exact,
+//     the quotient is FP64 in this order.  A block with n Q - S^2 = 0 (flat) is not scored.
+// D3: the disparity is the scored candidate of largest c, ties to the smaller d; none -> 0.
+//     A candidate is admissible when the other block lies in the image.
+// D4: the bottom matched row searches 1..d_max; row v searches the union over the matched
+//     columns k = u-1..u+1 of [l(k,v+1) - tau, l(k,v+1) + tau] clipped to 1..d_max, over the
+//     neighbours with l(k,v+1) > 0; with none of them, 1..d_max again.
+// D5: the right map is estimated the same way with the roles swapped (right block at x, left
+//     block at x + d), its own propagation, the same statistics.
+// D6: l(u,v) = l_lf(u,v) unless l_lf(u,v) = 0, u - l_lf(u,v) < 0, or
+//     |l_lf(u,v) - l_rt(u - l_lf(u,v), v)| > tr, in which case 0.
+namespace {
+struct StereoStats {
+    int W = 0, H = 0, rho = 0, n = 0;
+    std::vector<int64_t> S, Q;   // block sums at every matchable centre (0 elsewhere)
+};
+
+// Alg. "integral image initialisation" for I and I^2, then the four-reference block sums.
+StereoStats stereo_stats(const uint8_t* img, int64_t pitch, int W, int H, int rho) {
+    StereoStats st;
+    st.W = W; st.H = H; st.rho = rho; st.n = (2 * rho + 1) * (2 * rho + 1);
+    std::vector<int64_t> In((size_t)W * H), In2((size_t)W * H);
+    auto I = [&](int u, int v) { return (int64_t)img[(int64_t)v * pitch + u]; };
+    auto at = [&](std::vector<int64_t>& a, int u, int v) -> int64_t& { return a[(size_t)v * W + u]; };
+    at(In, 0, 0) = I(0, 0);
+    at(In2, 0, 0) = I(0, 0) * I(0, 0);
+    for (int u = 1; u < W; ++u) {
+        at(In, u, 0) = at(In, u - 1, 0) + I(u, 0);
+        at(In2, u, 0) = at(In2, u - 1, 0) + I(u, 0) * I(u, 0);
+    }
+    for (int v = 1; v < H; ++v) {
+        at(In, 0, v) = at(In, 0, v - 1) + I(0, v);
+        at(In2, 0, v) = at(In2, 0, v - 1) + I(0, v) * I(0, v);
+    }
+    for (int u = 1; u < W; ++u)
+        for (int v = 1; v < H; ++v) {
+            at(In, u, v) = at(In, u, v - 1) + at(In, u - 1, v) - at(In, u - 1, v - 1) + I(u, v);
+            at(In2, u, v) = at(In2, u, v - 1) + at(In2, u - 1, v) - at(In2, u - 1, v - 1) + I(u, v) * I(u, v);
+        }
+    // r1 = In(u+rho, v+rho), r2 = In(u-rho-1, v-rho-1), r3 = In(u-rho-1, v+rho), r4 = In(u+rho, v-rho-1),
+    // a reference left of column 0 or above row 0 being 0
+    auto ref = [&](std::vector<int64_t>& a, int u, int v) -> int64_t { return (u < 0 || v < 0) ? 0 : at(a, u, v); };
+    st.S.assign((size_t)W * H, 0);
+    st.Q.assign((size_t)W * H, 0);
+    for (int v = rho; v <= H - 1 - rho; ++v)
+        for (int u = rho; u <= W - 1 - rho; ++u) {
+            st.S[(size_t)v * W + u] = ref(In, u + rho, v + rho) + ref(In, u - rho - 1, v - rho - 1) -
+                                      ref(In, u - rho - 1, v + rho) - ref(In, u + rho, v - rho - 1);
+            st.Q[(size_t)v * W + u] = ref(In2, u + rho, v + rho) + ref(In2, u - rho - 1, v - rho - 1) -
+                                      ref(In2, u - rho - 1, v + rho) - ref(In2, u + rho, v - rho - 1);
+        }
+    return st;
+}
+
+// One disparity map by SRP.  ref_left = 1: blocks of `a` at u matched against `b` at u - d
+// (the left map); 0: `a` at x against `b` at x + d (the right map).
+void stereo_srp(const uint8_t* a, const uint8_t* b, int64_t pitch, const StereoStats& sa, const StereoStats& sb,
+                int d_max, int tau, int ref_left, uint8_t* out, double* cost_out) {
+    const int W = sa.W, H = sa.H, rho = sa.rho, n = sa.n;
+    auto A = [&](int u, int v) { return (int64_t)a[(int64_t)v * pitch + u]; };
+    auto B = [&](int u, int v) { return (int64_t)b[(int64_t)v * pitch + u]; };
+    for (int64_t i = 0; i < (int64_t)W * H; ++i) out[i] = 0;
+    std::vector<uint8_t> scan(d_max + 2);
+    for (int v = H - 1 - rho; v >= rho; --v) {
+        for (int u = rho; u <= W - 1 - rho; ++u) {
+            // D4: the search range
+            std::fill(scan.begin(), scan.end(), 0);
+            bool any = false;
+            if (v < H - 1 - rho) {
+                for (int k = u - 1; k <= u + 1; ++k) {
+                    if (k < rho || k > W - 1 - rho) continue;
+                    const int l = out[(int64_t)(v + 1) * W + k];
+                    if (l <= 0) continue;
+                    any = true;
+                    for (int d = l - tau; d <= l + tau; ++d)
+                        if (d >= 1 && d <= d_max) scan[d] = 1;
+                }
+            }
+            if (!any)
+                for (int d = 1; d <= d_max; ++d) scan[d] = 1;
+            const int64_t Sa = sa.S[(size_t)v * W + u], Qa = sa.Q[(size_t)v * W + u];
+            const int64_t Va = (int64_t)n * Qa - Sa * Sa;
+            int best = 0;
+            double bc = 0.0;
+            if (Va > 0) {
+                for (int d = 1; d <= d_max; ++d) {
+                    if (!scan[d]) continue;
+                    const int x = ref_left ? u - d : u + d;          // centre of the other block
+                    if (x < rho || x > W - 1 - rho) continue;
+                    const int64_t Sb = sb.S[(size_t)v * W + x], Qb = sb.Q[(size_t)v * W + x];
+                    const int64_t Vb = (int64_t)n * Qb - Sb * Sb;
+                    if (Vb <= 0) continue;
+                    int64_t P = 0;
+                    for (int j = v - rho; j <= v + rho; ++j)
+                        for (int i = -rho; i <= rho; ++i) P += A(u + i, j) * B(x + i, j);
+                    const double c = (double)((int64_t)n * P - Sa * Sb) / (std::sqrt((double)Va) * std::sqrt((double)Vb));
+                    if (best == 0 || c > bc) { best = d; bc = c; }
+                }
+            }
+            out[(int64_t)v * W + u] = (uint8_t)best;
+            if (cost_out) cost_out[(int64_t)v * W + u] = best ? bc : 0.0;
+        }
+    }
+}
+}  // namespace
+
+int ldref_stereo(const uint8_t* left, const uint8_t* right, int64_t pitch, int W, int H, int rho, int d_max, int tau,
+                 int tr_lrc, uint8_t* disp_lf, uint8_t* disp_rt, uint8_t* disp, double* cost_lf) {
+    if (rho < 1 || rho > 7 || d_max < 1 || d_max > 255 || tau < 0 || tr_lrc < 0 || W < 2 * rho + 1 || H < 2 * rho + 1)
+        return -1;
+    const StereoStats sl = stereo_stats(left, pitch, W, H, rho), sr = stereo_stats(right, pitch, W, H, rho);
+    std::vector<uint8_t> lf((size_t)W * H), rt((size_t)W * H);
+    stereo_srp(left, right, pitch, sl, sr, d_max, tau, 1, lf.data(), cost_lf);
+    stereo_srp(right, left, pitch, sr, sl, d_max, tau, 0, rt.data(), nullptr);
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            const int l = lf[(size_t)v * W + u];
+            int o = 0;
+            if (l > 0 && u - l >= 0 && std::abs(l - (int)rt[(size_t)v * W + (u - l)]) <= tr_lrc) o = l;
+            disp[(size_t)v * W + u] = (uint8_t)o;
+        }
+    if (disp_lf) std::memcpy(disp_lf, lf.data(), lf.size());
+    if (disp_rt) std::memcpy(disp_rt, rt.data(), rt.size());
+    return 0;
+}
+
+// The block statistics alone (pinned separately): S and Q at every matchable centre.
+int ldref_stereo_stats(const uint8_t* img, int64_t pitch, int W, int H, int rho, int64_t* S, int64_t* Q) {
+    if (rho < 1 || W < 2 * rho + 1 || H < 2 * rho + 1) return -1;
+    const StereoStats st = stereo_stats(img, pitch, W, H, rho);
+    std::memcpy(S, st.S.data(), sizeof(int64_t) * st.S.size());
+    std::memcpy(Q, st.Q.data(), sizeof(int64_t) * st.Q.size());
+    return 0;
+}
+
+// ------------------------------------------------------------------------------------
 // Lane tracking across frames.  The paper names a tracking algorithm as future work (Sec. 4)
 // without defining one; this is the reading taken (T1..T5).  T1: a track is a lane's start
 // column x on row v_max with a rate dx in columns per frame; a frame first predicts every

@@ -87,6 +87,9 @@ def lib():
         L.ldref_sobel.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, _P32, _P32]
         L.ldref_track_update.argtypes = [C.POINTER(TrackState), _P32, C.c_int, C.c_int, C.c_double, C.c_double,
                                          C.c_double, C.c_int]
+        L.ldref_stereo.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, _PD]
+        L.ldref_stereo_stats.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, _P64, _P64]
         L.ldref_bilateral.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_float, C.c_float,
                                       C.c_int, C.c_void_p, C.c_int64, _PF]
         L.ldref_sample.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, _P32]
@@ -343,6 +346,33 @@ def sobel(grey: np.ndarray):
     gy = np.zeros((H, W), np.int32)
     lib().ldref_sobel(grey.ctypes.data, grey.strides[0], W, H, _p32(gx), _p32(gy))
     return gx, gy
+
+
+def stereo(left: np.ndarray, right: np.ndarray, d_max: int = 128, rho: int = 3, tau: int = 1, tr_lrc: int = 3):
+    """Disparity maps of a rectified pair (Sec. 2.1): (checked map, left map, right map, left
+    costs), u8 maps with 0 for no match."""
+    left = np.ascontiguousarray(left, dtype=np.uint8)
+    right = np.ascontiguousarray(right, dtype=np.uint8)
+    assert left.shape == right.shape
+    H, W = left.shape
+    lf, rt, out = (np.zeros((H, W), np.uint8) for _ in range(3))
+    cost = np.zeros((H, W))
+    rc = lib().ldref_stereo(left.ctypes.data, right.ctypes.data, W, W, H, rho, d_max, tau, tr_lrc, lf.ctypes.data,
+                            rt.ctypes.data, out.ctypes.data, _pd(cost))
+    if rc != 0:
+        raise ValueError("stereo: invalid arguments")
+    return out, lf, rt, cost
+
+
+def stereo_stats(img: np.ndarray, rho: int = 3):
+    """Block sums S and sums of squares Q from the integral images (0 off the matchable centres)."""
+    img = np.ascontiguousarray(img, dtype=np.uint8)
+    H, W = img.shape
+    S = np.zeros((H, W), np.int64)
+    Q = np.zeros((H, W), np.int64)
+    if lib().ldref_stereo_stats(img.ctypes.data, W, W, H, rho, S.ctypes.data_as(_P64), Q.ctypes.data_as(_P64)) != 0:
+        raise ValueError("stereo_stats: invalid arguments")
+    return S, Q
 
 
 class TrackState(C.Structure):
