@@ -232,6 +232,30 @@ void ld_track_params_default(ld_track_params* tp);
 ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const int32_t* state_index,
                    const ld_track_params* tp, void* hip_stream);
 
+/* Disparity maps of rectified stereo pairs (Sec. 2.1): NCC block matching on block statistics
+ * memorised from integral images (Eq. ncc_1, Eq. sigma_l_1, Eq. sigma_r_1), search range
+ * propagation row by row from the bottom (Eq. srp), left-right consistency check (Alg. "LRC
+ * check").  A pixel is matched when its (2 rho + 1)^2 block lies in the image; disparity 0 means
+ * no match, so the search runs over 1..d_max (the frame object's d_max, <= 255); a candidate
+ * counts when the other image's block lies in the image and neither block is flat.  The cost is
+ * (n P - S_l S_r) / (sqrt(n Q_l - S_l^2) sqrt(n Q_r - S_r^2)) (S block sums, Q sums of squares, P
+ * the sum of products, n = (2 rho + 1)^2): integers exactly, the quotient in FP64 in that order;
+ * the largest cost wins, ties to the smaller disparity.  The bottom matched row searches
+ * 1..d_max; row v the union of [l - tau, l + tau] over the matched neighbours u-1..u+1 of row
+ * v+1 with l > 0, or 1..d_max when none has one.  The right map is the same search from the
+ * right image (the left block at x + d).  The checked map keeps l(u, v) when u - l >= 0 and
+ * |l(u, v) - l_right(u - l, v)| <= tr_lrc, else 0.  The paper uses rho 3, tau 1, tr_lrc 3.
+ *  left, right       : device uint8 n x height x pitch (n = active frames), pitches >= width.
+ *  disp_out          : device uint8 n x height x disp_pitch: the checked map (an LD_DISP_U8
+ *                      disparity for ld_vdisp / ld_detect).
+ *  disp_lf, disp_rt  : device uint8 n x height x width each: the left and right maps (the
+ *                      check needs both).
+ *  rho 1..5, tau 0..255, tr_lrc >= 0.  LD_E_INVAL otherwise, or when the sweep's rows do not fit
+ *  in LDS (width above about 2900 at rho 3). */
+ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pitch, const uint8_t* right, int64_t right_pitch,
+                    int32_t rho, int32_t tau, int32_t tr_lrc, uint8_t* disp_out, int64_t disp_pitch, uint8_t* disp_lf,
+                    uint8_t* disp_rt, void* hip_stream);
+
 /* Scratch of ld_detect_noalloc, per GPU (64 MiB). */
 #define LD_NOALLOC_SCRATCH_BYTES (64ull << 20)
 

@@ -140,6 +140,8 @@ def lib():
         L.ld_track_params_default.restype = None
         L.ld_track.argtypes = [vp, vp, vp, vp, C.POINTER(ld_track_params), vp]
         L.ld_track.restype = i32
+        L.ld_stereo.argtypes = [vp, vp, i64, vp, i64, i32, i32, i32, vp, i64, vp, vp, vp]
+        L.ld_stereo.restype = i32
         L.ld_server_tracks.argtypes = [vp, i32, vp]
         L.ld_server_tracks.restype = i32
         for name in ("ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params", "ld_cnn_forward",
@@ -160,7 +162,7 @@ EXPORTED = ["ld_params_default", "ld_frame_create", "ld_frame_destroy", "ld_fram
             "ld_cnn_config_default", "ld_cnn_create", "ld_cnn_destroy", "ld_cnn_set_params", "ld_cnn_get_params",
             "ld_cnn_forward", "ld_cnn_labels", "ld_cnn_train_step", "ld_detect_pruned", "ld_detect_noalloc",
             "ld_cnn_save", "ld_cnn_load", "ld_bilateral", "ld_track_params_default", "ld_track",
-            "ld_server_tracks"]
+            "ld_server_tracks", "ld_stereo"]
 KERNELS = ["k_vdisp_hist", "k_vdisp_fit", "k_edges", "k_vpx_fit", "k_energy", "k_peaks", "k_cnn_fwd", "k_seed",
            "k_vpx_window", "k_cand_mask", "k_vpx_ransac"]
 
@@ -253,6 +255,12 @@ def track_params_default(**overrides) -> ld_track_params:
 
 def ld_track(f, lanes, states, state_index, tp, stream):
     return lib().ld_track(f, lanes, states, state_index, C.byref(tp) if tp is not None else None, stream)
+
+
+def ld_stereo(f, left, left_pitch, right, right_pitch, rho, tau, tr_lrc, disp_out, disp_pitch, disp_lf, disp_rt,
+              stream):
+    return lib().ld_stereo(f, left, left_pitch, right, right_pitch, rho, tau, tr_lrc, disp_out, disp_pitch, disp_lf,
+                           disp_rt, stream)
 
 
 def ld_bilateral(f, grey, grey_pitch, out, out_pitch, rho, sigma_s, sigma_r, road_rows, stream):
@@ -531,6 +539,13 @@ class Detector:
         """Bilateral pre-filter of the grey images into `out` (uint8, same shape)."""
         check(ld_bilateral(self.handle, _ptr(grey), self._pitch(grey), _ptr(out), self._pitch(out), int(rho),
                            float(sigma_s), float(sigma_r), 1 if road_rows else 0, _stream()), "ld_bilateral")
+
+    def stereo(self, left, right, disp_out, disp_lf, disp_rt, rho: int = 3, tau: int = 1, tr_lrc: int = 3):
+        """Disparity maps of rectified pairs (uint8 [n, H, W] tensors): the checked map into
+        disp_out, the left and right maps into disp_lf / disp_rt (contiguous)."""
+        check(ld_stereo(self.handle, _ptr(left), self._pitch(left), _ptr(right), self._pitch(right), int(rho),
+                        int(tau), int(tr_lrc), _ptr(disp_out), self._pitch(disp_out), _ptr(disp_lf), _ptr(disp_rt),
+                        _stream()), "ld_stereo")
 
     def track(self, lanes, states, state_index=None, params: ld_track_params | None = None):
         """Fold the lanes of the active frames into device tracker states (uint8 tensor of

@@ -309,6 +309,58 @@ def make_hard(kind: str, seed: int = 0, idx: int = 0):
     return grey, disp, sc
 
 
+def make_stereo(config: str = "c2", seed: int = 0, idx: int = 0):
+    """A rectified stereo pair of the road scene: (left grey, right grey, true left disparity
+    (float32, 0 above the horizon), scene).  The road texture (asphalt noise and lane markings)
+    is drawn on a canvas wider than the frame; the left view is its first `width` columns with
+    the obstacle blocks pasted in, the right view samples each road row at u = x + f(v) (linear
+    interpolation; rows above the horizon unshifted) and pastes every block shifted left by its
+    own, whole-pixel disparity; the right camera adds N(0, 1) sensor noise.  config "c2":
+    1242x375 with ~10 % obstacle pixels; "c1": 320x96 without obstacles."""
+    if config == "c2":
+        sc = scene_c2(seed, idx)
+        width_fn, frac = marking_width, 0.10
+    elif config == "c1":
+        sc = scene_c1(seed)
+        width_fn, frac = None, 0.0
+    else:
+        raise ValueError(config)
+    rng = _rng(seed ^ 0x57E5, idx)
+    W, H = sc.width, sc.height
+    obstacles = _obstacles(sc, rng, frac) if frac > 0 else []
+    margin = sc.d_max + 8
+    wide = Scene(**{**sc.__dict__, "width": W + margin, "obstacles": [], "paint": []})
+    road, _ = _render(wide, rng, disp_noise=0.0, dropout=0.0, dash_k=None, width_fn=width_fn)
+    road = road.astype(np.float64)
+    left = road[:, :W].copy()
+    right = np.empty((H, W))
+    xs = np.arange(W, dtype=np.float64)
+    cols = np.arange(W + margin, dtype=np.float64)
+    gt = np.zeros((H, W), np.float32)
+    for v in range(H):
+        d = float(sc.f(v)) if v >= sc.v0 else 0.0
+        right[v] = np.interp(xs + d, cols, road[v])
+        gt[v] = d
+    for (u0, u1, vt, vb, _) in obstacles:
+        d_o = int(round(float(sc.f(vb))))
+        r0, r1 = max(0, vt), min(H - 1, vb)
+        if r0 > r1 or d_o < 1:
+            continue
+        patch = rng.normal(60.0, 4.0, size=(r1 - r0 + 1, u1 - u0 + 1))
+        for x0, img in ((u0, left), (u0 - d_o, right)):
+            a, b = max(0, x0), min(W - 1, x0 + u1 - u0)
+            if a <= b:
+                img[r0:r1 + 1, a:b + 1] = patch[:, a - x0:b - x0 + 1]
+        a, b = max(0, u0), min(W - 1, u1)
+        if a <= b:
+            gt[r0:r1 + 1, a:b + 1] = d_o
+    right = right + rng.normal(0.0, 1.0, size=right.shape)
+    left = np.clip(np.rint(left), 0, 255).astype(np.uint8)
+    right = np.clip(np.rint(right), 0, 255).astype(np.uint8)
+    sc.obstacles = obstacles
+    return left, right, gt, sc
+
+
 def scene_c3(seed: int, idx: int) -> Scene:
     rng = _rng(seed, 1 << 41)
     q = rng.uniform(-6e-5, 6e-5)

@@ -56,6 +56,7 @@ def test_invalid_arguments_rejected_before_any_device_call(L):
     assert ld.ld_detect(None, None, 0, None, 0, None, None, None, None, None) == ld.LD_E_INVAL
     assert ld.ld_sync(None) == ld.LD_E_INVAL
     assert ld.ld_bilateral(None, None, 0, None, 0, 5, 300.0, 0.3, 0, None) == ld.LD_E_INVAL
+    assert ld.ld_stereo(None, None, 0, None, 0, 3, 1, 3, None, 0, None, None, None) == ld.LD_E_INVAL
     assert ld.ld_frame_destroy(None) == ld.LD_OK
 
 
