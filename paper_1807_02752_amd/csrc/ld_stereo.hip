@@ -29,7 +29,8 @@
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 512;        // sweep threads: 8 waves, two sweeps per CU (LDS) keep 4 waves per SIMD
+constexpr int kTL = 256;       // consistency check threads
 
 size_t stereo_lds(int W, int rho) {
     const size_t Wp = (size_t)(W + 3) / 4 * 4;
@@ -46,7 +47,20 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                                                int W, int H, const int32_t* nact, int nframes, int d_max, int tau,
                                                uint8_t* lf, uint8_t* rt) {
     constexpr int K = 2 * RHO + 1, N = K * K;
+    constexpr int NW = (K + 3) / 4;                                   // words of a block row
+    constexpr uint32_t kLastMask = (K % 4 == 0) ? 0xFFFFFFFFu : ((1u << (8 * (K % 4))) - 1u);
     extern __shared__ __align__(16) unsigned char smem[];
+    // NW words of a row holding bytes o .. o + 4 NW - 1 (rows start on a word; the word after a
+    // row's last byte lies in the LDS allocation, its bytes are cleared or unused)
+    auto fetch = [&](const uint8_t* row, int o, uint32_t (&w)[NW]) {
+        const uint32_t* r = reinterpret_cast<const uint32_t*>(row) + (o >> 2);
+        const uint32_t s = (uint32_t)(o & 3);
+        uint32_t x[NW + 1];
+#pragma unroll
+        for (int k = 0; k <= NW; ++k) x[k] = r[k];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(x[k + 1], x[k], s);
+    };
     const int b = blockIdx.x, t = threadIdx.x;
     const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
     if (b >= nf) return;
@@ -135,13 +149,14 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                     lo = max(lo, 1);
                     hi = min(hi, d_max);
                 }
-                // the map's own block in registers
-                int A[K][K];
+                // the map's own block in registers, four bytes a word (the bytes past the block
+                // are cleared, so the partner block's extra bytes add nothing)
+                uint32_t A[K][NW];
 #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const int slot = (v - RHO + j) % K;
-#pragma unroll
-                    for (int i = 0; i < K; ++i) A[j][i] = ringA[slot * Wp + u - RHO + i];
+                    fetch(ringA + slot * Wp, u - RHO, A[j]);
+                    A[j][NW - 1] &= kLastMask;
                 }
                 const int64_t Sa = S_a[u];
                 const double da = sq_a[u];
@@ -156,14 +171,16 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                     if (x < RHO || x > W - 1 - RHO) continue;
                     const double db = sq_b[x];
                     if (!(db > 0.0)) continue;
-                    int P = 0;
+                    uint32_t P = 0;
 #pragma unroll
                     for (int j = 0; j < K; ++j) {
                         const int slot = (v - RHO + j) % K;
+                        uint32_t Bw[NW];
+                        fetch(ringB + slot * Wp, x - RHO, Bw);
 #pragma unroll
-                        for (int i = 0; i < K; ++i) P += A[j][i] * (int)ringB[slot * Wp + x - RHO + i];
+                        for (int k = 0; k < NW; ++k) P = __builtin_amdgcn_udot4(A[j][k], Bw[k], P, false);
                     }
-                    const double c = (double)((int64_t)N * P - Sa * (int64_t)S_b[x]) / (da * db);
+                    const double c = (double)((int64_t)N * (int64_t)P - Sa * (int64_t)S_b[x]) / (da * db);
                     if (best == 0 || c > bc) { best = d; bc = c; }
                 }
             }
@@ -176,12 +193,12 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
 }
 
 // l(u) = l_left(u) unless it is 0, u - l(u) < 0 or |l(u) - l_right(u - l(u))| > tr
-__global__ __launch_bounds__(kT) void k_lrc(const uint8_t* lf, const uint8_t* rt, int W, int H, const int32_t* nact,
+__global__ __launch_bounds__(kTL) void k_lrc(const uint8_t* lf, const uint8_t* rt, int W, int H, const int32_t* nact,
                                             int nframes, int tr, uint8_t* out, int64_t op) {
     const int b = blockIdx.y;
     const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
     if (b >= nf) return;
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kTL + threadIdx.x;
     if (i >= (int64_t)W * H) return;
     const int v = (int)(i / W), u = (int)(i % W);
     const int64_t base = (int64_t)b * H * W;
@@ -222,7 +239,7 @@ extern "C" ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pit
             default: launch<5>(left, left_pitch, right, right_pitch, V, tau, disp_lf, disp_rt, st); break;
         }
         const int64_t px = (int64_t)V.W * V.H;
-        hipLaunchKernelGGL(k_lrc, dim3((unsigned)((px + kT - 1) / kT), V.active), dim3(kT), 0, st, disp_lf, disp_rt,
+        hipLaunchKernelGGL(k_lrc, dim3((unsigned)((px + kTL - 1) / kTL), V.active), dim3(kTL), 0, st, disp_lf, disp_rt,
                            V.W, V.H, V.nact, V.active, tr_lrc, disp_out, disp_pitch);
     }
     if (hipGetLastError() != hipSuccess) return LD_E_HIP;
