@@ -251,7 +251,7 @@ ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state* states, co
  *  disp_lf, disp_rt  : device uint8 n x height x width each: the left and right maps (the
  *                      check needs both).
  *  rho 1..5, tau 0..255, tr_lrc >= 0.  LD_E_INVAL otherwise, or when the sweep's rows do not fit
- *  in LDS (width above about 2900 at rho 3). */
+ *  in LDS (width above about 2800 at rho 3). */
 ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pitch, const uint8_t* right, int64_t right_pitch,
                     int32_t rho, int32_t tau, int32_t tr_lrc, uint8_t* disp_out, int64_t disp_pitch, uint8_t* disp_lf,
                     uint8_t* disp_rt, void* hip_stream);

@@ -14,11 +14,16 @@
 // x + d); the check keeps l(u) when |l(u) - l_right(u - l(u))| <= tr.
 //
 // Layout: one workgroup per (frame, map) sweeps the rows from the bottom; the 2 rho + 1 image
-// rows of both images sit in an LDS ring (one new row per step), the block sums of the current
-// row are formed from column sums in LDS, and the square roots of the block variances are kept
-// per column (FP64), so a candidate costs its 2 rho + 1 squared products, a subtraction, a
-// multiplication and a division.  The propagation makes the rows of a frame sequential; frames
-// and the two maps are independent workgroups.
+// rows of both images sit in an LDS ring (one new row per step, fetched from HBM while the row
+// before it is matched), the column sums over the ring follow each new row incrementally, the
+// block sums of a row come from the column sums four columns a thread, and the square roots of
+// the block variances are kept per column (FP64), so a candidate costs its 2 rho + 1 rows of
+// byte dot products, a subtraction, a multiplication and a division.  A pixel with a matched
+// neighbour below searches its few propagated candidates in its own lane; a pixel without one
+// (every pixel of the first row) searches all of 1..d_max, which would hold up the 63 other
+// lanes of its wave, so such pixels go to a queue that whole waves take one pixel at a time,
+// a candidate per lane.  The propagation makes the rows of a frame sequential; frames and the
+// two maps are independent workgroups.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,16 +35,23 @@
 namespace {
 
 constexpr int kT = 512;        // sweep threads: 8 waves, two sweeps per CU (LDS) keep 4 waves per SIMD
+constexpr int kWaves = kT / 64;
+constexpr int kRowWords = 2;   // words of a new row per thread and image: widths up to 4 kT kRowWords
+constexpr int kPad = 8;        // zero columns on both sides of the column sums (block sums four at a time)
 constexpr int kTL = 256;       // consistency check threads
+constexpr int kNone = 1 << 20; // an absent neighbour in the sorted propagation bounds
+
+__host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) / 16 * 16; }
 
 size_t stereo_lds(int W, int rho) {
     const size_t Wp = (size_t)(W + 3) / 4 * 4;
     const size_t rows = 2 * (size_t)rho + 1;
-    return 2 * rows * Wp                       // image rings (u8)
-           + 4 * sizeof(int32_t) * W           // column sums S, Q of both images
-           + 2 * sizeof(int32_t) * W           // block sums S of both images
-           + 2 * sizeof(double) * W            // sqrt of the block variances of both images
-           + 2 * Wp;                           // disparities of the previous and the current row
+    return round16(2 * rows * Wp)                      // image rings (u8)
+           + 4 * sizeof(int32_t) * (Wp + 2 * kPad)     // column sums S, Q of both images
+           + 2 * sizeof(int32_t) * Wp                  // block sums S of both images
+           + 2 * sizeof(double) * Wp                   // sqrt of the block variances of both images
+           + 2 * Wp                                    // disparities of the previous and the current row
+           + sizeof(uint16_t) * Wp + 16;               // queue of full-range pixels, its length
 }
 
 template <int RHO>
@@ -49,6 +61,7 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     constexpr int K = 2 * RHO + 1, N = K * K;
     constexpr int NW = (K + 3) / 4;                                   // words of a block row
     constexpr uint32_t kLastMask = (K % 4 == 0) ? 0xFFFFFFFFu : ((1u << (8 * (K % 4))) - 1u);
+    constexpr int kC = (RHO + 3) / 4;                                 // column-sum quads either side
     extern __shared__ __align__(16) unsigned char smem[];
     // NW words of a row holding bytes o .. o + 4 NW - 1 (rows start on a word; the word after a
     // row's last byte lies in the LDS allocation, its bytes are cleared or unused)
@@ -71,19 +84,21 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     const int64_t pa = is_left ? lp : rp, pb = is_left ? rp : lp;
     uint8_t* out = (is_left ? lf : rt) + (int64_t)b * H * W;
     const int sgn = is_left ? -1 : 1;
-    const int Wp = (W + 3) / 4 * 4;
+    const int Wp = (W + 3) / 4 * 4, Wq = Wp / 4;
     uint8_t* ringA = smem;
     uint8_t* ringB = ringA + K * Wp;
-    int32_t* colS_a = reinterpret_cast<int32_t*>(ringB + K * Wp);
-    int32_t* colQ_a = colS_a + W;
-    int32_t* colS_b = colQ_a + W;
-    int32_t* colQ_b = colS_b + W;
-    int32_t* S_a = colQ_b + W;
-    int32_t* S_b = S_a + W;
-    double* sq_a = reinterpret_cast<double*>(S_b + W);        // 8-byte aligned: 2 K Wp + 24 W bytes before it
-    double* sq_b = sq_a + W;
-    uint8_t* prev = reinterpret_cast<uint8_t*>(sq_b + W);
+    int32_t* colS_a = reinterpret_cast<int32_t*>(smem + round16(2 * (size_t)K * Wp)) + kPad;
+    int32_t* colQ_a = colS_a + Wp + 2 * kPad;
+    int32_t* colS_b = colQ_a + Wp + 2 * kPad;
+    int32_t* colQ_b = colS_b + Wp + 2 * kPad;
+    int32_t* S_a = colQ_b + Wp + kPad;
+    int32_t* S_b = S_a + Wp;
+    double* sq_a = reinterpret_cast<double*>(S_b + Wp);
+    double* sq_b = sq_a + Wp;
+    uint8_t* prev = reinterpret_cast<uint8_t*>(sq_b + Wp);
     uint8_t* cur = prev + Wp;
+    uint16_t* queue = reinterpret_cast<uint16_t*>(cur + Wp);
+    int* qn = reinterpret_cast<int*>(queue + Wp);
     // rows outside the matched band are 0 (every row when no block fits)
     const bool none = W < K || H < K;
     for (int v = 0; v < H; ++v) {
@@ -91,104 +106,226 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         for (int u = t; u < W; u += kT) out[(int64_t)v * W + u] = 0;
     }
     if (none) return;
-    auto load_row = [&](int v) {
+    // the first 2 rho + 1 rows (slot v mod K), bytes past the width cleared; the column sums
+    const int vb = H - 1 - RHO;
+    for (int v = vb - RHO; v <= vb + RHO; ++v) {
         const int slot = v % K;
-        for (int u = t; u < W; u += kT) {
-            ringA[slot * Wp + u] = ga[(int64_t)v * pa + u];
-            ringB[slot * Wp + u] = gb[(int64_t)v * pb + u];
+        for (int u = t; u < Wp; u += kT) {
+            ringA[slot * Wp + u] = u < W ? ga[(int64_t)v * pa + u] : 0;
+            ringB[slot * Wp + u] = u < W ? gb[(int64_t)v * pb + u] : 0;
+        }
+    }
+    for (int i = t; i < kPad; i += kT) {
+        colS_a[-1 - i] = colQ_a[-1 - i] = colS_b[-1 - i] = colQ_b[-1 - i] = 0;
+        colS_a[Wp + i] = colQ_a[Wp + i] = colS_b[Wp + i] = colQ_b[Wp + i] = 0;
+    }
+    if (t == 0) *qn = 0;
+    __syncthreads();
+    for (int u = t; u < Wp; u += kT) {
+        int sa = 0, qa = 0, sb = 0, qb = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int x = ringA[j * Wp + u], y = ringB[j * Wp + u];
+            sa += x; qa += x * x; sb += y; qb += y * y;
+        }
+        colS_a[u] = sa; colQ_a[u] = qa; colS_b[u] = sb; colQ_b[u] = qb;
+    }
+    // the candidate of disparity d for the pixel at u: its cost against the best so far, the
+    // first strictly larger one kept (with d increasing that leaves ties to the smaller d)
+    auto score = [&](const uint32_t (&A)[K][NW], int u, int64_t Sa, double da, int d, int vlo, int& best,
+                     double& bc) {
+        const int x = u + sgn * d;
+        if (x < RHO || x > W - 1 - RHO) return;
+        const double db = sq_b[x];
+        if (!(db > 0.0)) return;
+        uint32_t P = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int slot = (vlo + j) % K;
+            uint32_t Bw[NW];
+            fetch(ringB + slot * Wp, x - RHO, Bw);
+#pragma unroll
+            for (int k = 0; k < NW; ++k) P = __builtin_amdgcn_udot4(A[j][k], Bw[k], P, false);
+        }
+        const double c = (double)((int64_t)N * (int64_t)P - Sa * (int64_t)S_b[x]) / (da * db);
+        if (best == 0 || c > bc) { best = d; bc = c; }
+    };
+    auto own_block = [&](int u, int vlo, uint32_t (&A)[K][NW]) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            fetch(ringA + ((vlo + j) % K) * Wp, u - RHO, A[j]);
+            A[j][NW - 1] &= kLastMask;        // the bytes past the block are cleared
         }
     };
-    const int vb = H - 1 - RHO;
-    for (int v = vb - RHO; v <= vb + RHO; ++v) load_row(v);
     for (int v = vb; v >= RHO; --v) {
-        if (v < vb) load_row(v - RHO);
+        const bool more = v > RHO;             // a row v - rho - 1 follows
+        const int vlo = v - RHO;
         __syncthreads();
-        // column sums over the block's rows, then the block sums and sqrt of n Q - S^2
-        for (int u = t; u < W; u += kT) {
-            int sa = 0, qa = 0, sb = 0, qb = 0;
+        // block sums and sqrt(n Q - S^2), four columns a thread (0 where no block fits)
+        for (int g = t; g < Wq; g += kT) {
+            int cs[4][4 * (2 * kC + 1)];
+            const int32_t* arr[4] = {colS_a, colQ_a, colS_b, colQ_b};
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const int slot = (v - RHO + j) % K;
-                const int x = ringA[slot * Wp + u], y = ringB[slot * Wp + u];
-                sa += x; qa += x * x; sb += y; qb += y * y;
+            for (int a = 0; a < 4; ++a) {
+#pragma unroll
+                for (int c = -kC; c <= kC; ++c) {
+                    const int4 q = *reinterpret_cast<const int4*>(arr[a] + 4 * (g + c));
+                    cs[a][4 * (c + kC) + 0] = q.x; cs[a][4 * (c + kC) + 1] = q.y;
+                    cs[a][4 * (c + kC) + 2] = q.z; cs[a][4 * (c + kC) + 3] = q.w;
+                }
             }
-            colS_a[u] = sa; colQ_a[u] = qa; colS_b[u] = sb; colQ_b[u] = qb;
+            int bs[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                int s = 0;
+#pragma unroll
+                for (int m = -RHO; m <= RHO; ++m) s += cs[a][4 * kC + m];
+                bs[a][0] = s;
+#pragma unroll
+                for (int i = 1; i < 4; ++i) {
+                    s += cs[a][4 * kC + i + RHO] - cs[a][4 * kC + i - 1 - RHO];
+                    bs[a][i] = s;
+                }
+            }
+            int4 oa, ob;
+            double qa4[4], qb4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 4 * g + i;
+                const bool fits = u >= RHO && u <= W - 1 - RHO;
+                const int sa = fits ? bs[0][i] : 0, sb = fits ? bs[2][i] : 0;
+                const int va = N * bs[1][i] - bs[0][i] * bs[0][i], vbv = N * bs[3][i] - bs[2][i] * bs[2][i];
+                qa4[i] = fits && va > 0 ? sqrt((double)va) : 0.0;
+                qb4[i] = fits && vbv > 0 ? sqrt((double)vbv) : 0.0;
+                (&oa.x)[i] = sa; (&ob.x)[i] = sb;
+            }
+            *reinterpret_cast<int4*>(S_a + 4 * g) = oa;
+            *reinterpret_cast<int4*>(S_b + 4 * g) = ob;
+#pragma unroll
+            for (int i = 0; i < 4; i += 2) {
+                *reinterpret_cast<double2*>(sq_a + 4 * g + i) = make_double2(qa4[i], qa4[i + 1]);
+                *reinterpret_cast<double2*>(sq_b + 4 * g + i) = make_double2(qb4[i], qb4[i + 1]);
+            }
         }
         __syncthreads();
-        for (int u = t; u < W; u += kT) {
-            if (u < RHO || u > W - 1 - RHO) continue;
-            int sa = 0, qa = 0, sb = 0, qb = 0;
+        // the next row from HBM while this one is matched: four bytes a word for words t and
+        // t + kT, byte loads at clamped positions (their values are masked when the words are
+        // put together), so that nothing waits for them before the row is done
+        uint32_t ra[kRowWords][4], rb[kRowWords][4];
+        {
+            const uint8_t* pa0 = ga + (int64_t)(more ? vlo - 1 : vlo) * pa;
+            const uint8_t* pb0 = gb + (int64_t)(more ? vlo - 1 : vlo) * pb;
 #pragma unroll
-            for (int i = -RHO; i <= RHO; ++i) {
-                sa += colS_a[u + i]; qa += colQ_a[u + i]; sb += colS_b[u + i]; qb += colQ_b[u + i];
-            }
-            S_a[u] = sa; S_b[u] = sb;
-            const int va = N * qa - sa * sa, vbv = N * qb - sb * sb;
-            sq_a[u] = va > 0 ? sqrt((double)va) : 0.0;
-            sq_b[u] = vbv > 0 ? sqrt((double)vbv) : 0.0;
+            for (int k = 0; k < kRowWords; ++k)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int u = min(4 * (t + k * kT) + i, W - 1);
+                    ra[k][i] = pa0[u];
+                    rb[k][i] = pb0[u];
+                }
         }
-        __syncthreads();
+        // pixels with a matched neighbour below: the union of [l - tau, l + tau] over those
+        // neighbours, in increasing d, in the pixel's own lane; the others are queued
         const bool first = v == vb;
         for (int u = t; u < W; u += kT) {
             int best = 0;
             if (u >= RHO && u <= W - 1 - RHO && sq_a[u] > 0.0) {
-                // the search range: [lo, hi] and a membership test over the matched neighbours
                 int l0 = 0, l1 = 0, l2 = 0;
                 if (!first) {
                     l0 = u - 1 >= RHO ? prev[u - 1] : 0;
                     l1 = prev[u];
                     l2 = u + 1 <= W - 1 - RHO ? prev[u + 1] : 0;
                 }
-                const bool any = (l0 | l1 | l2) != 0;
-                int lo = 1, hi = d_max;
-                if (any) {
-                    lo = 1 << 30; hi = -1;
-                    if (l0) { lo = min(lo, l0 - tau); hi = max(hi, l0 + tau); }
-                    if (l1) { lo = min(lo, l1 - tau); hi = max(hi, l1 + tau); }
-                    if (l2) { lo = min(lo, l2 - tau); hi = max(hi, l2 + tau); }
-                    lo = max(lo, 1);
-                    hi = min(hi, d_max);
-                }
-                // the map's own block in registers, four bytes a word (the bytes past the block
-                // are cleared, so the partner block's extra bytes add nothing)
-                uint32_t A[K][NW];
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const int slot = (v - RHO + j) % K;
-                    fetch(ringA + slot * Wp, u - RHO, A[j]);
-                    A[j][NW - 1] &= kLastMask;
-                }
-                const int64_t Sa = S_a[u];
-                const double da = sq_a[u];
-                double bc = 0.0;
-                for (int d = lo; d <= hi; ++d) {
-                    if (any) {
-                        const bool in = (l0 && abs(d - l0) <= tau) || (l1 && abs(d - l1) <= tau) ||
-                                        (l2 && abs(d - l2) <= tau);
-                        if (!in) continue;
+                if ((l0 | l1 | l2) == 0) {
+                    queue[atomicAdd(qn, 1)] = (uint16_t)u;
+                } else {
+                    int s0 = l0 ? l0 : kNone, s1 = l1 ? l1 : kNone, s2 = l2 ? l2 : kNone;
+                    {   // s0 <= s1 <= s2
+                        const int a = min(s0, s1), c = max(s0, s1);
+                        const int hi3 = max(c, s2), mid = min(c, s2);
+                        s0 = min(a, mid); s1 = max(a, mid); s2 = hi3;
                     }
-                    const int x = u + sgn * d;
-                    if (x < RHO || x > W - 1 - RHO) continue;
-                    const double db = sq_b[x];
-                    if (!(db > 0.0)) continue;
-                    uint32_t P = 0;
-#pragma unroll
-                    for (int j = 0; j < K; ++j) {
-                        const int slot = (v - RHO + j) % K;
-                        uint32_t Bw[NW];
-                        fetch(ringB + slot * Wp, x - RHO, Bw);
-#pragma unroll
-                        for (int k = 0; k < NW; ++k) P = __builtin_amdgcn_udot4(A[j][k], Bw[k], P, false);
+                    uint32_t A[K][NW];
+                    own_block(u, vlo, A);
+                    const int64_t Sa = S_a[u];
+                    const double da = sq_a[u];
+                    double bc = 0.0;
+                    int d = max(s0 - tau, 1), hi = min(s0 + tau, d_max);
+                    while (true) {
+                        if (d > hi) {
+                            if (s1 >= kNone) break;
+                            d = max(d, s1 - tau);
+                            hi = min(s1 + tau, d_max);
+                            s1 = s2; s2 = kNone;
+                            continue;
+                        }
+                        score(A, u, Sa, da, d, vlo, best, bc);
+                        ++d;
                     }
-                    const double c = (double)((int64_t)N * (int64_t)P - Sa * (int64_t)S_b[x]) / (da * db);
-                    if (best == 0 || c > bc) { best = d; bc = c; }
                 }
             }
             cur[u] = (uint8_t)best;
-            out[(int64_t)v * W + u] = (uint8_t)best;
         }
         __syncthreads();
-        for (int u = t; u < W; u += kT) prev[u] = cur[u];
+        // queued pixels: one wave a pixel, candidates 1 + lane, 65 + lane, ..., then the
+        // best (largest cost, then smallest d) over the wave
+        const int nq = *qn;
+        if (nq > 0) {
+            const int wv = t >> 6, lane = t & 63;
+            for (int q = wv; q < nq; q += kWaves) {
+                const int u = queue[q];
+                uint32_t A[K][NW];
+                own_block(u, vlo, A);
+                const int64_t Sa = S_a[u];
+                const double da = sq_a[u];
+                int best = 0;
+                double bc = 0.0;
+                for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, vlo, best, bc);
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double oc = __shfl_xor(bc, off);
+                    const int od = __shfl_xor(best, off);
+                    if (od != 0 && (best == 0 || oc > bc || (oc == bc && od < best))) { best = od; bc = oc; }
+                }
+                if (lane == 0) cur[u] = (uint8_t)best;
+            }
+            __syncthreads();
+        }
+        // the next row replaces row v + rho in the ring and in the column sums; the row out
+        if (more) {
+            const int slot = (v + RHO) % K;
+            uint32_t* wa = reinterpret_cast<uint32_t*>(ringA + slot * Wp);
+            uint32_t* wb = reinterpret_cast<uint32_t*>(ringB + slot * Wp);
+#pragma unroll
+            for (int k = 0; k < kRowWords; ++k) {
+                const int g = t + k * kT;
+                if (g >= Wq) continue;
+                uint32_t na = 0, nb = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (4 * g + i < W) {
+                        na |= ra[k][i] << (8 * i);
+                        nb |= rb[k][i] << (8 * i);
+                    }
+                }
+                const uint32_t oa = wa[g], ob = wb[g];
+                wa[g] = na; wb[g] = nb;
+                int4 s1 = *reinterpret_cast<int4*>(colS_a + 4 * g), q1 = *reinterpret_cast<int4*>(colQ_a + 4 * g);
+                int4 s2 = *reinterpret_cast<int4*>(colS_b + 4 * g), q2 = *reinterpret_cast<int4*>(colQ_b + 4 * g);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int xn = (na >> (8 * i)) & 0xFF, xo = (oa >> (8 * i)) & 0xFF;
+                    const int yn = (nb >> (8 * i)) & 0xFF, yo = (ob >> (8 * i)) & 0xFF;
+                    (&s1.x)[i] += xn - xo; (&q1.x)[i] += xn * xn - xo * xo;
+                    (&s2.x)[i] += yn - yo; (&q2.x)[i] += yn * yn - yo * yo;
+                }
+                *reinterpret_cast<int4*>(colS_a + 4 * g) = s1; *reinterpret_cast<int4*>(colQ_a + 4 * g) = q1;
+                *reinterpret_cast<int4*>(colS_b + 4 * g) = s2; *reinterpret_cast<int4*>(colQ_b + 4 * g) = q2;
+            }
+        }
+        for (int u = t; u < W; u += kT) out[(int64_t)v * W + u] = cur[u];
+        if (t == 0) *qn = 0;
+        uint8_t* tmp = prev; prev = cur; cur = tmp;
     }
 }
 
@@ -228,7 +365,7 @@ extern "C" ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pit
         return LD_E_INVAL;
     if (rho < 1 || rho > 5 || tau < 0 || tau > 255 || tr_lrc < 0 || V.d_max > 255) return LD_E_INVAL;
     if (left_pitch < V.W || right_pitch < V.W || disp_pitch < V.W) return LD_E_INVAL;
-    if (stereo_lds(V.W, rho) > 160 * 1024) return LD_E_INVAL;
+    if (stereo_lds(V.W, rho) > 160 * 1024 || V.W > 4 * kT * kRowWords) return LD_E_INVAL;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (V.active > 0) {
         switch (rho) {
