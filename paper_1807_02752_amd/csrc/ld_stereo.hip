@@ -14,8 +14,10 @@
 // x + d); the check keeps l(u) when |l(u) - l_right(u - l(u))| <= tr.
 //
 // Layout: one workgroup per (frame, map) sweeps the rows from the bottom; the 2 rho + 1 image
-// rows of both images sit in an LDS ring (one new row per step, fetched from HBM while the row
-// before it is matched), the column sums over the ring follow each new row incrementally, the
+// rows of both images sit in an LDS ring (one new row per step into the slot of the row that
+// leaves, fetched from HBM while the row before it is matched), stored word-interleaved (word g
+// of all slots together) so that a block's words are constant offsets from one address; the sum
+// of products takes the rows in slot order for both blocks, which leaves it unchanged.  The column sums over the ring follow each new row incrementally, the
 // block sums of a row come from the column sums four columns a thread, and the square roots of
 // the block variances are kept per column (FP64), so a candidate costs its 2 rho + 1 rows of
 // byte dot products, a subtraction, a multiplication and a division.  A pixel with a matched
@@ -63,14 +65,15 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     constexpr uint32_t kLastMask = (K % 4 == 0) ? 0xFFFFFFFFu : ((1u << (8 * (K % 4))) - 1u);
     constexpr int kC = (RHO + 3) / 4;                                 // column-sum quads either side
     extern __shared__ __align__(16) unsigned char smem[];
-    // NW words of a row holding bytes o .. o + 4 NW - 1 (rows start on a word; the word after a
-    // row's last byte lies in the LDS allocation, its bytes are cleared or unused)
-    auto fetch = [&](const uint8_t* row, int o, uint32_t (&w)[NW]) {
-        const uint32_t* r = reinterpret_cast<const uint32_t*>(row) + (o >> 2);
+    // NW words holding bytes o .. o + 4 NW - 1 of the row in slot j of a ring whose word g of
+    // slot j is word g K + j (the words past a row's last byte lie in the LDS allocation, their
+    // bytes are cleared or unused)
+    auto fetch = [&](const uint32_t* ring, int j, int o, uint32_t (&w)[NW]) {
+        const uint32_t* r = ring + (o >> 2) * K + j;
         const uint32_t s = (uint32_t)(o & 3);
         uint32_t x[NW + 1];
 #pragma unroll
-        for (int k = 0; k <= NW; ++k) x[k] = r[k];
+        for (int k = 0; k <= NW; ++k) x[k] = r[k * K];
 #pragma unroll
         for (int k = 0; k < NW; ++k) w[k] = __builtin_amdgcn_alignbyte(x[k + 1], x[k], s);
     };
@@ -85,8 +88,10 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     uint8_t* out = (is_left ? lf : rt) + (int64_t)b * H * W;
     const int sgn = is_left ? -1 : 1;
     const int Wp = (W + 3) / 4 * 4, Wq = Wp / 4;
-    uint8_t* ringA = smem;
-    uint8_t* ringB = ringA + K * Wp;
+    uint32_t* ringA = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* ringB = ringA + K * Wq;
+    uint8_t* ringA8 = smem;
+    uint8_t* ringB8 = reinterpret_cast<uint8_t*>(ringB);
     int32_t* colS_a = reinterpret_cast<int32_t*>(smem + round16(2 * (size_t)K * Wp)) + kPad;
     int32_t* colQ_a = colS_a + Wp + 2 * kPad;
     int32_t* colS_b = colQ_a + Wp + 2 * kPad;
@@ -111,8 +116,9 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     for (int v = vb - RHO; v <= vb + RHO; ++v) {
         const int slot = v % K;
         for (int u = t; u < Wp; u += kT) {
-            ringA[slot * Wp + u] = u < W ? ga[(int64_t)v * pa + u] : 0;
-            ringB[slot * Wp + u] = u < W ? gb[(int64_t)v * pb + u] : 0;
+            const int at = ((u >> 2) * K + slot) * 4 + (u & 3);
+            ringA8[at] = u < W ? ga[(int64_t)v * pa + u] : 0;
+            ringB8[at] = u < W ? gb[(int64_t)v * pb + u] : 0;
         }
     }
     for (int i = t; i < kPad; i += kT) {
@@ -125,35 +131,40 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         int sa = 0, qa = 0, sb = 0, qb = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int x = ringA[j * Wp + u], y = ringB[j * Wp + u];
+            const int at = ((u >> 2) * K + j) * 4 + (u & 3);
+            const int x = ringA8[at], y = ringB8[at];
             sa += x; qa += x * x; sb += y; qb += y * y;
         }
         colS_a[u] = sa; colQ_a[u] = qa; colS_b[u] = sb; colQ_b[u] = qb;
     }
     // the candidate of disparity d for the pixel at u: its cost against the best so far, the
-    // first strictly larger one kept (with d increasing that leaves ties to the smaller d)
-    auto score = [&](const uint32_t (&A)[K][NW], int u, int64_t Sa, double da, int d, int vlo, int& best,
-                     double& bc) {
+    // first strictly larger one kept (with d increasing that leaves ties to the smaller d).  The
+    // numerator n P - S_a S_b is exact in 32 bits (each product below 2^30 for rho <= 5); a
+    // candidate whose block leaves the image or is flat is scored at a stand-in position and
+    // not taken
+    auto score = [&](const uint32_t (&A)[K][NW], int u, int Sa, double da, int d, int& best, double& bc) {
         const int x = u + sgn * d;
-        if (x < RHO || x > W - 1 - RHO) return;
-        const double db = sq_b[x];
-        if (!(db > 0.0)) return;
+        const bool inr = x >= RHO && x <= W - 1 - RHO;
+        const int xc = inr ? x : RHO;
+        const double db = sq_b[xc];
         uint32_t P = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int slot = (vlo + j) % K;
             uint32_t Bw[NW];
-            fetch(ringB + slot * Wp, x - RHO, Bw);
+            fetch(ringB, j, xc - RHO, Bw);
 #pragma unroll
             for (int k = 0; k < NW; ++k) P = __builtin_amdgcn_udot4(A[j][k], Bw[k], P, false);
         }
-        const double c = (double)((int64_t)N * (int64_t)P - Sa * (int64_t)S_b[x]) / (da * db);
-        if (best == 0 || c > bc) { best = d; bc = c; }
+        const int num = N * (int)P - Sa * S_b[xc];
+        const double c = (double)num / (da * db);
+        const bool take = inr && db > 0.0 && (best == 0 || c > bc);
+        best = take ? d : best;
+        bc = take ? c : bc;
     };
-    auto own_block = [&](int u, int vlo, uint32_t (&A)[K][NW]) {
+    auto own_block = [&](int u, uint32_t (&A)[K][NW]) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            fetch(ringA + ((vlo + j) % K) * Wp, u - RHO, A[j]);
+            fetch(ringA, j, u - RHO, A[j]);
             A[j][NW - 1] &= kLastMask;        // the bytes past the block are cleared
         }
     };
@@ -245,22 +256,30 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                         const int hi3 = max(c, s2), mid = min(c, s2);
                         s0 = min(a, mid); s1 = max(a, mid); s2 = hi3;
                     }
+                    // the union as up to three disjoint runs in increasing order
+                    int a0 = max(s0 - tau, 1), b0 = min(s0 + tau, d_max), a1 = 1, b1 = 0, a2 = 1, b2 = 0;
+                    if (s1 < kNone) {
+                        const int lo = s1 - tau, hi = min(s1 + tau, d_max);
+                        if (lo <= b0 + 1) b0 = max(b0, hi); else { a1 = lo; b1 = hi; }
+                    }
+                    if (s2 < kNone) {
+                        const int lo = s2 - tau, hi = min(s2 + tau, d_max);
+                        if (b1 >= a1) {
+                            if (lo <= b1 + 1) b1 = max(b1, hi); else { a2 = lo; b2 = hi; }
+                        } else {
+                            if (lo <= b0 + 1) b0 = max(b0, hi); else { a1 = lo; b1 = hi; }
+                        }
+                    }
                     uint32_t A[K][NW];
-                    own_block(u, vlo, A);
-                    const int64_t Sa = S_a[u];
+                    own_block(u, A);
+                    const int Sa = S_a[u];
                     const double da = sq_a[u];
                     double bc = 0.0;
-                    int d = max(s0 - tau, 1), hi = min(s0 + tau, d_max);
+                    int d = a0, e = b0;
                     while (true) {
-                        if (d > hi) {
-                            if (s1 >= kNone) break;
-                            d = max(d, s1 - tau);
-                            hi = min(s1 + tau, d_max);
-                            s1 = s2; s2 = kNone;
-                            continue;
-                        }
-                        score(A, u, Sa, da, d, vlo, best, bc);
-                        ++d;
+                        for (; d <= e; ++d) score(A, u, Sa, da, d, best, bc);
+                        if (a1 > b1) break;
+                        d = a1; e = b1; a1 = a2; b1 = b2; a2 = 1; b2 = 0;
                     }
                 }
             }
@@ -275,12 +294,12 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
             for (int q = wv; q < nq; q += kWaves) {
                 const int u = queue[q];
                 uint32_t A[K][NW];
-                own_block(u, vlo, A);
-                const int64_t Sa = S_a[u];
+                own_block(u, A);
+                const int Sa = S_a[u];
                 const double da = sq_a[u];
                 int best = 0;
                 double bc = 0.0;
-                for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, vlo, best, bc);
+                for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, best, bc);
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) {
                     const double oc = __shfl_xor(bc, off);
@@ -294,8 +313,6 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         // the next row replaces row v + rho in the ring and in the column sums; the row out
         if (more) {
             const int slot = (v + RHO) % K;
-            uint32_t* wa = reinterpret_cast<uint32_t*>(ringA + slot * Wp);
-            uint32_t* wb = reinterpret_cast<uint32_t*>(ringB + slot * Wp);
 #pragma unroll
             for (int k = 0; k < kRowWords; ++k) {
                 const int g = t + k * kT;
@@ -308,8 +325,8 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                         nb |= rb[k][i] << (8 * i);
                     }
                 }
-                const uint32_t oa = wa[g], ob = wb[g];
-                wa[g] = na; wb[g] = nb;
+                const uint32_t oa = ringA[g * K + slot], ob = ringB[g * K + slot];
+                ringA[g * K + slot] = na; ringB[g * K + slot] = nb;
                 int4 s1 = *reinterpret_cast<int4*>(colS_a + 4 * g), q1 = *reinterpret_cast<int4*>(colQ_a + 4 * g);
                 int4 s2 = *reinterpret_cast<int4*>(colS_b + 4 * g), q2 = *reinterpret_cast<int4*>(colQ_b + 4 * g);
 #pragma unroll
