@@ -275,11 +275,17 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                     const int Sa = S_a[u];
                     const double da = sq_a[u];
                     double bc = 0.0;
+                    // one loop over all the candidates (a lane's runs follow each other
+                    // without waiting for the other lanes' runs to end)
+                    const int n = (b0 - a0 + 1) + max(b1 - a1 + 1, 0) + max(b2 - a2 + 1, 0);
                     int d = a0, e = b0;
-                    while (true) {
-                        for (; d <= e; ++d) score(A, u, Sa, da, d, best, bc);
-                        if (a1 > b1) break;
-                        d = a1; e = b1; a1 = a2; b1 = b2; a2 = 1; b2 = 0;
+                    for (int k = 0; k < n; ++k) {
+                        score(A, u, Sa, da, d, best, bc);
+                        const bool nx = d == e;
+                        d = nx ? a1 : d + 1;
+                        e = nx ? b1 : e;
+                        a1 = nx ? a2 : a1;
+                        b1 = nx ? b2 : b1;
                     }
                 }
             }
