@@ -137,14 +137,14 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         }
         colS_a[u] = sa; colQ_a[u] = qa; colS_b[u] = sb; colQ_b[u] = qb;
     }
-    // the candidate of disparity d for the pixel at u: its cost against the best so far, the
-    // first strictly larger one kept (with d increasing that leaves ties to the smaller d).  The
-    // numerator n P - S_a S_b is exact in 32 bits (each product below 2^30 for rho <= 5); a
-    // candidate whose block leaves the image or is flat is scored at a stand-in position and
-    // not taken
+    // the candidate of disparity d for the pixel at u: its cost against the best so far (bc
+    // starts at -inf), the first strictly larger one kept (with d increasing that leaves ties to
+    // the smaller d).  The numerator n P - S_a S_b is exact in 32 bits (each product below 2^30
+    // for rho <= 5); a candidate whose block leaves the image or is flat is scored at a stand-in
+    // position and not taken
     auto score = [&](const uint32_t (&A)[K][NW], int u, int Sa, double da, int d, int& best, double& bc) {
         const int x = u + sgn * d;
-        const bool inr = x >= RHO && x <= W - 1 - RHO;
+        const bool inr = (unsigned)(x - RHO) <= (unsigned)(W - 1 - 2 * RHO);
         const int xc = inr ? x : RHO;
         const double db = sq_b[xc];
         uint32_t P = 0;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         }
         const int num = N * (int)P - Sa * S_b[xc];
         const double c = (double)num / (da * db);
-        const bool take = inr && db > 0.0 && (best == 0 || c > bc);
+        const bool take = inr & (db > 0.0) & (c > bc);
         best = take ? d : best;
         bc = take ? c : bc;
     };
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                     own_block(u, A);
                     const int Sa = S_a[u];
                     const double da = sq_a[u];
-                    double bc = 0.0;
+                    double bc = -__builtin_inf();
                     // one loop over all the candidates (a lane's runs follow each other
                     // without waiting for the other lanes' runs to end)
                     const int n = (b0 - a0 + 1) + max(b1 - a1 + 1, 0) + max(b2 - a2 + 1, 0);
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                 const int Sa = S_a[u];
                 const double da = sq_a[u];
                 int best = 0;
-                double bc = 0.0;
+                double bc = -__builtin_inf();
                 for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, best, bc);
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) {
