@@ -292,10 +292,24 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
             cur[u] = (uint8_t)best;
         }
         __syncthreads();
-        // queued pixels: one wave a pixel, candidates 1 + lane, 65 + lane, ..., then the
-        // best (largest cost, then smallest d) over the wave
+        // queued pixels: many (the first row) one a lane over all of 1..d_max; few one a wave,
+        // candidates 1 + lane, 65 + lane, ..., then the best (largest cost, then smallest d)
+        // over the wave
         const int nq = *qn;
-        if (nq > 0) {
+        if (nq >= kT / 2) {
+            for (int q = t; q < nq; q += kT) {
+                const int u = queue[q];
+                uint32_t A[K][NW];
+                own_block(u, A);
+                const int Sa = S_a[u];
+                const double da = sq_a[u];
+                int best = 0;
+                double bc = -__builtin_inf();
+                for (int d = 1; d <= d_max; ++d) score(A, u, Sa, da, d, best, bc);
+                cur[u] = (uint8_t)best;
+            }
+            __syncthreads();
+        } else if (nq > 0) {
             const int wv = t >> 6, lane = t & 63;
             for (int q = wv; q < nq; q += kWaves) {
                 const int u = queue[q];
