@@ -49,8 +49,10 @@ constexpr int kMaxLds = 160 * 1024;   // LDS bytes a workgroup may hold on gfx95
 struct Dev {
     int W, H, D1, W2, half, fmt, d_max, B;
     int hist_rows;      // rows binned by one histogram workgroup
+    int Hm;             // row stride of myT: H rounded up to 32, so a histogram workgroup's rows
+                        // of one disparity fill whole 128-byte lines
     ld_params P;
-    int32_t* myT;       // B x D1 x H   v-disparity counts, transposed (m_y(d, .) contiguous)
+    int32_t* myT;       // B x D1 x Hm  v-disparity counts, transposed (m_y(d, .) contiguous)
     uint8_t* back_y;    // B x D1 x H   v-disparity DP backtrace (tau)
     int32_t* my_pts;    // B x 2 x D1   DP path points with votes: rows, then disparities
     FitRes* fit;        // B x 2        beta, gamma
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_vdisp_hist(Dev d, const uint8_t* dis
     __syncthreads();
     for (int i = t; i < rows * D1; i += kBlock) {
         const int dd = i / rows, r = i % rows;
-        d.myT[((int64_t)b * D1 + dd) * H + v0 + r] = hist[r * D1 + dd];
+        d.myT[((int64_t)b * D1 + dd) * d.Hm + v0 + r] = hist[r * D1 + dd];
     }
     if (vdisp_out) {
         for (int i = t; i < rows * D1; i += kBlock) {
@@ -545,11 +547,12 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
     const int bm_words = (H + 31) / 32;
     uint8_t* win = reinterpret_cast<uint8_t*>(bitmap + bm_words);   // kVdWalk x kVdWalkCols
     uint8_t* back = d.back_y + (int64_t)b * D1 * H;
-    const int32_t* myT = d.myT + (int64_t)b * D1 * H;
+    const int Hm = d.Hm;
+    const int32_t* myT = d.myT + (int64_t)b * D1 * Hm;
     const int tau_max = d.P.tau_y_max, lam = d.P.lambda_y;
 
     for (int v = t; v < H; v += nt) {
-        E0[v] = -myT[(int64_t)d_max * H + v] * 16;
+        E0[v] = -myT[(int64_t)d_max * Hm + v] * 16;
         d.rowcnt[(int64_t)b * H + v] = 0;
     }
     if (t < kVdPad) { E0[H + t] = kVdPadKey; E1[H + t] = kVdPadKey; }
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 #pragma unroll
     for (int k = 0; k < kVdRows; ++k) {
         const int v = t + k * nt;
-        nxt[k] = (d_max >= 1 && v < H) ? myT[(int64_t)(d_max - 1) * H + v] : 0;
+        nxt[k] = (d_max >= 1 && v < H) ? myT[(int64_t)(d_max - 1) * Hm + v] : 0;
     }
     __syncthreads();
     int* Ec = E0;
@@ -576,7 +579,7 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
 #pragma unroll
             for (int k = 0; k < kVdRows; ++k) {
                 const int v = t + k * nt;
-                nxt[k] = v < H ? myT[(int64_t)(dd - 1) * H + v] : 0;
+                nxt[k] = v < H ? myT[(int64_t)(dd - 1) * Hm + v] : 0;
             }
         }
 #pragma unroll
@@ -645,7 +648,7 @@ __global__ __launch_bounds__(1024) void k_vdisp_fit(Dev d, const uint64_t* strea
         int base = 0;
         for (int c0 = 0; c0 <= d_max; c0 += nt) {
             const int dd = c0 + t;
-            const bool pred = dd <= d_max && myT[(int64_t)dd * H + cur[dd]] > 0;
+            const bool pred = dd <= d_max && myT[(int64_t)dd * Hm + cur[dd]] > 0;
             const uint64_t bal = __ballot(pred);
             if (lane == 0) S.wsum[wave] = __popcll(bal);
             __syncthreads();
@@ -2310,7 +2313,7 @@ constexpr int kRegions = 18;
 size_t frame_layout(int width, int height, int batch, int d_max, size_t* off, size_t* sz) {
     const size_t B = (size_t)batch, H = (size_t)height, W = (size_t)width, D1 = (size_t)d_max + 1, W2 = 2 * (size_t)width;
     const size_t s[kRegions] = {
-        B * D1 * H * 4,                 // myT
+        B * D1 * ((H + 31) / 32 * 32) * 4,   // myT (rows padded to 32)
         B * D1 * H,                     // back_y
         B * 2 * D1 * 4,                 // my_pts
         B * 2 * sizeof(FitRes),         // fit
@@ -2390,6 +2393,7 @@ ld_status init_dev(Dev& d, int32_t width, int32_t height, int32_t batch, int32_t
     d.W = width; d.H = height; d.D1 = d_max + 1; d.W2 = 2 * width; d.half = width / 2; d.fmt = fmt;
     d.d_max = d_max; d.B = batch; d.P = P;
     d.hist_rows = std::max(kHistGroup, std::min(32, (8192 / d.D1) / kHistGroup * kHistGroup));
+    d.Hm = (height + 31) / 32 * 32;
     return LD_OK;
 }
 
