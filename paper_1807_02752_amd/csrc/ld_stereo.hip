@@ -40,7 +40,9 @@ constexpr int kT = 512;        // sweep threads: 8 waves, two sweeps per CU (LDS
 constexpr int kWaves = kT / 64;
 constexpr int kRowWords = 2;   // words of a new row per thread and image: widths up to 4 kT kRowWords
 constexpr int kPad = 8;        // zero columns on both sides of the column sums (block sums four at a time)
-constexpr int kTL = 256;       // consistency check threads
+constexpr int kTL = 320;       // consistency check threads (a 1242-pixel row in one workgroup)
+constexpr int kLrcPx = 4;      // consistency check pixels a thread
+constexpr int kLrcRows = 8;    // consistency check rows a workgroup
 constexpr int kNone = 1 << 20; // an absent neighbour in the sorted propagation bounds
 
 __host__ __device__ constexpr size_t round16(size_t x) { return (x + 15) / 16 * 16; }
@@ -366,20 +368,32 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     }
 }
 
-// l(u) = l_left(u) unless it is 0, u - l(u) < 0 or |l(u) - l_right(u - l(u))| > tr
+// l(u) = l_left(u) unless it is 0, u - l(u) < 0 or |l(u) - l_right(u - l(u))| > tr.  A workgroup
+// takes kLrcRows rows of a frame (grid: row groups, frames), kLrcPx consecutive pixels a thread.
+template <int PX>
 __global__ __launch_bounds__(kTL) void k_lrc(const uint8_t* lf, const uint8_t* rt, int W, int H, const int32_t* nact,
                                             int nframes, int tr, uint8_t* out, int64_t op) {
     const int b = blockIdx.y;
     const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
     if (b >= nf) return;
-    const int64_t i = (int64_t)blockIdx.x * kTL + threadIdx.x;
-    if (i >= (int64_t)W * H) return;
-    const int v = (int)(i / W), u = (int)(i % W);
-    const int64_t base = (int64_t)b * H * W;
-    const int l = lf[base + i];
-    int o = 0;
-    if (l > 0 && u - l >= 0 && abs(l - (int)rt[base + (int64_t)v * W + (u - l)]) <= tr) o = l;
-    out[((int64_t)b * H + v) * op + u] = (uint8_t)o;
+    for (int v = blockIdx.x * kLrcRows; v < min(H, (int)(blockIdx.x + 1) * kLrcRows); ++v) {
+        const uint8_t* L = lf + ((int64_t)b * H + v) * W;
+        const uint8_t* R = rt + ((int64_t)b * H + v) * W;
+        uint8_t* O = out + ((int64_t)b * H + v) * op;
+        for (int u0 = threadIdx.x * PX; u0 < W; u0 += kTL * PX) {
+            uint8_t l[PX];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) l[k] = L[min(u0 + k, W - 1)];
+#pragma unroll
+            for (int k = 0; k < PX; ++k) {
+                const int u = u0 + k, lk = l[k];
+                if (u >= W) break;
+                int o = 0;
+                if (lk > 0 && u - lk >= 0 && abs(lk - (int)R[u - lk]) <= tr) o = lk;
+                O[u] = (uint8_t)o;
+            }
+        }
+    }
 }
 
 template <int RHO>
@@ -412,9 +426,9 @@ extern "C" ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pit
             case 4: launch<4>(left, left_pitch, right, right_pitch, V, tau, disp_lf, disp_rt, st); break;
             default: launch<5>(left, left_pitch, right, right_pitch, V, tau, disp_lf, disp_rt, st); break;
         }
-        const int64_t px = (int64_t)V.W * V.H;
-        hipLaunchKernelGGL(k_lrc, dim3((unsigned)((px + kTL - 1) / kTL), V.active), dim3(kTL), 0, st, disp_lf, disp_rt,
-                           V.W, V.H, V.nact, V.active, tr_lrc, disp_out, disp_pitch);
+        const unsigned gx = (unsigned)((V.H + kLrcRows - 1) / kLrcRows);
+        hipLaunchKernelGGL(k_lrc<kLrcPx>, dim3(gx, V.active), dim3(kTL), 0, st, disp_lf, disp_rt, V.W, V.H, V.nact,
+                           V.active, tr_lrc, disp_out, disp_pitch);
     }
     if (hipGetLastError() != hipSuccess) return LD_E_HIP;
     return ldi_frame_set_last(f, hip_stream);
