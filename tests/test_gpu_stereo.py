@@ -68,6 +68,27 @@ def test_shifted_textures_ragged_and_parameters(H, W, rho, tau, pad):
     _check(L, R, 24, got, rho=rho, tau=tau)
 
 
+@pytest.mark.parametrize("W,d_max", [(200, 150), (640, 150), (90, 40)])
+def test_pixels_without_matched_neighbours_in_later_rows(W, d_max):
+    """A flat band (blocks of zero variance are not matched) leaves the row above it with no
+    matched neighbour below: those pixels search all of 1..d_max again, a wave per pixel when
+    few (several candidates a lane for d_max above 64) and a lane per pixel when many."""
+    rng = np.random.default_rng(W + d_max)
+    H = 60
+    L = rng.integers(0, 256, (2, H, W)).astype(np.uint8)
+    R = rng.integers(0, 256, (2, H, W)).astype(np.uint8)
+    for b in range(2):
+        for v in range(H):
+            d = 5 + (v * (b + 2)) // 11
+            R[b, v, :W - d] = np.clip(L[b, v, d:].astype(int) + rng.integers(-4, 5, W - d), 0, 255)
+        L[b, 20:31] = 100
+        R[b, 20:31] = 100
+    got = _stereo_gpu(L, R, d_max)
+    _check(L, R, d_max, got)
+    assert not got[1][:, 24:27].any()          # the flat rows are not matched
+    assert got[1][:, 16, 3:-3].any()           # the rows above them are matched again
+
+
 def test_flat_tiny_and_invalid():
     ld = _ld()
     flat = np.full((1, 20, 30), 77, np.uint8)
