@@ -1323,16 +1323,18 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
 //
 // One workgroup per frame.  First q is computed for every road edge (each wave a group of rows)
 // into a per-edge buffer.  Then the road rows are swept upwards.  At the step of row v every
-// thread pushes its NC columns of the dense q row v-4 (scattered into LDS during the previous
-// step) into a 9-row register ring (rows v-4..v+4) and forms V(x, v) = sum_y s_y C(x, v+y),
-// C = vertical 7-row sums, with the zero padding of M_0 outside the image, while the edges of
-// row v-5 are scattered into the other q row; after the step's one barrier the column owners
-// form M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) (terms outside the image dropped)
-// into one of two LDS rows, and every candidate adds M_1 at its track column of row v+1.  The
-// q, V and M_1 rows are double-buffered by row parity, so one barrier per row orders every
-// write before its reads.  Rows are padded to the NC * 256 columns the threads own (the
-// columns past W hold zeros), so the column loops carry no bounds test.  The row loop is
-// unrolled nine times so that the ring rotates by renaming registers instead of moving them.
+// thread pushes its NC consecutive columns of the dense q row v-4 (scattered into LDS during the
+// previous step) into a 9-row register ring (rows v-4..v+4) and forms V(x, v) = sum_y s_y
+// C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0 outside the image (a uniform
+// branch: rows strictly inside take both neighbours without a select), while the edges of row
+// v-5 are scattered into the other q row; after the step's one barrier the column owners form
+// M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) from three-column sums shared by their
+// consecutive columns (terms outside the image dropped, on the few edge lanes only) into one of
+// two LDS rows, and every candidate adds M_1 at its track column of row v+1.  The q, V and M_1
+// rows are double-buffered by row parity, so one barrier per row orders every write before its
+// reads.  Rows are padded to the NC * 256 columns the threads own (the columns past W hold
+// zeros), so the column loops carry no bounds test.  The row loop is unrolled nine times so
+// that the ring rotates by renaming registers instead of moving them.
 // mode 0 / 1: G_x w_g with the exponent as printed / squared; mode 2: the prior work's vote
 // |grad| cos(theta_e - theta_Vp) = t . (p - V_p) / |p - V_p| = -dot / |r|, in FP64 (no gate)
 __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
@@ -1447,7 +1449,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         constexpr int S = decltype(Sc)::value;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const int u = t + k * kBlock;
+            const int u = t * NC + k;
             ring[k][S] = q[u];
             q[u] = 0.0f;
         }
@@ -1495,33 +1497,52 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         const int par = v & 1;
         push(Sc, qb(par));               // row v - 4 (same parity as v)
         const bool up = v >= 1, dn = v + 1 <= v_max;   // M_0 is zero outside the image rows
+        // (uniform over the workgroup: the rows strictly inside the image take both terms
+        // without a per-column select)
+        auto vcol = [&](auto both) {
 #pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const int u = t + k * kBlock;
-            float r[9];
+            for (int k = 0; k < NC; ++k) {
+                const int u = t * NC + k;
+                float r[9];
 #pragma unroll
-            for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
-            const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
-            const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
-            const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
-            const float cp1 = (s5 + r[7]) + r[8];   // C(v+1): rows v-2..v+4
-            float V = 2.0f * c0;
-            V += up ? cm1 : 0.0f;
-            V += dn ? cp1 : 0.0f;
-            Vp(par)[u + 2] = V;
-        }
+                for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
+                const float s5 = (((r[2] + r[3]) + r[4]) + r[5]) + r[6];
+                const float cm1 = (r[0] + r[1]) + s5;   // C(v-1): rows v-4..v+2
+                const float c0 = (r[1] + s5) + r[7];    // C(v):   rows v-3..v+3
+                const float cp1 = (s5 + r[7]) + r[8];   // C(v+1): rows v-2..v+4
+                float V = 2.0f * c0;
+                if constexpr (decltype(both)::value) {
+                    V += cm1;
+                    V += cp1;
+                } else {
+                    V += up ? cm1 : 0.0f;
+                    V += dn ? cp1 : 0.0f;
+                }
+                Vp(par)[u + 2] = V;
+            }
+        };
+        if (up && dn) vcol(std::bool_constant<true>{}); else vcol(std::bool_constant<false>{});
         scatter_next(qb(par ^ 1));       // row v - 5
         prefetch(v - 6);
         __syncthreads();
         float* mrow = mb(par);
         const float* vr = Vp(par);
+        // a thread's NC consecutive columns share their three-column sums: the sum over columns
+        // u-2 .. u (M_0 at u-1) is the one over u .. u+2 (M_0 at u+1) of the column two to the left
+        float vv[NC + 4], T3[NC + 2];
+#pragma unroll
+        for (int j = 0; j < NC + 4; ++j) vv[j] = vr[t * NC + j];
+#pragma unroll
+        for (int j = 0; j < NC + 2; ++j) T3[j] = (vv[j] + vv[j + 1]) + vv[j + 2];
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const int u = t + k * kBlock;
-            const float g1 = (vr[u + 2] + vr[u + 3]) + vr[u + 4];   // columns u .. u+2 (M_0 at u+1)
-            const float g2 = (vr[u] + vr[u + 1]) + vr[u + 2];       // columns u-2 .. u (M_0 at u-1)
-            const float m1 = (u + 1 <= W - 1 ? g1 : 0.0f) - (u >= 1 ? g2 : 0.0f);
-            mrow[u] = u < W ? m1 : 0.0f;
+            const int u = t * NC + k;
+            const float g1 = T3[k + 2];   // columns u .. u+2 (M_0 at u+1)
+            const float g2 = T3[k];       // columns u-2 .. u (M_0 at u-1)
+            float m1 = g1 - g2;
+            // the columns at the image edges and past it (a few lanes of a few waves)
+            if (u < 1 || u >= W - 1) m1 = u < W ? (u + 1 <= W - 1 ? g1 : 0.0f) - (u >= 1 ? g2 : 0.0f) : 0.0f;
+            mrow[u] = m1;
         }
         if (v < v_max) candidates(mb(par ^ 1));   // row v + 1
         coef(v);                       // for this row's candidates in the next step
