@@ -232,8 +232,9 @@ void ld_track_params_default(ld_track_params* tp);
 ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const int32_t* state_index,
                    const ld_track_params* tp, void* hip_stream);
 
-/* Disparity maps of rectified stereo pairs (Sec. 2.1): NCC block matching on block statistics
- * memorised from integral images (Eq. ncc_1, Eq. sigma_l_1, Eq. sigma_r_1), search range
+/* Disparity maps of rectified stereo pairs (Sec. 2.1): NCC block matching on memorised block
+ * statistics (Eq. ncc_1, Eq. sigma_l_1, Eq. sigma_r_1; the paper forms them from integral
+ * images, the sweep here from running column sums, the same integers), search range
  * propagation row by row from the bottom (Eq. srp), left-right consistency check (Alg. "LRC
  * check").  A pixel is matched when its (2 rho + 1)^2 block lies in the image; disparity 0 means
  * no match, so the search runs over 1..d_max (the frame object's d_max, <= 255); a candidate
