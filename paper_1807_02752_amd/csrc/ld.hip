@@ -1323,18 +1323,19 @@ __global__ __launch_bounds__(kRansacThreads) void k_vpx_ransac(Dev d, const uint
 //
 // One workgroup per frame.  First q is computed for every road edge (each wave a group of rows)
 // into a per-edge buffer.  Then the road rows are swept upwards.  At the step of row v every
-// thread pushes its NC consecutive columns of the dense q row v-4 (scattered into LDS during the
-// previous step) into a 9-row register ring (rows v-4..v+4) and forms V(x, v) = sum_y s_y
-// C(x, v+y), C = vertical 7-row sums, with the zero padding of M_0 outside the image (a uniform
-// branch: rows strictly inside take both neighbours without a select), while the edges of row
-// v-5 are scattered into the other q row; after the step's one barrier the column owners form
-// M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) from three-column sums shared by their
-// consecutive columns (terms outside the image dropped, on the few edge lanes only) into one of
-// two LDS rows, and every candidate adds M_1 at its track column of row v+1.  The q, V and M_1
-// rows are double-buffered by row parity, so one barrier per row orders every write before its
-// reads.  Rows are padded to the NC * 256 columns the threads own (the columns past W hold
-// zeros), so the column loops carry no bounds test.  The row loop is unrolled nine times so
-// that the ring rotates by renaming registers instead of moving them.
+// thread pushes its NC columns (consecutive when NC is odd, a stride coprime with the LDS
+// banks; else t, t + 256, ...) of the dense q row v-4 (scattered into LDS during the previous
+// step) into a 9-row register ring (rows v-4..v+4) and forms V(x, v) = sum_y s_y C(x, v+y),
+// C = vertical 7-row sums, with the zero padding of M_0 outside the image (a uniform branch:
+// rows strictly inside take both neighbours without a select), while the edges of row v-5 are
+// scattered into the other q row; after the step's one barrier the column owners form
+// M_1(u, v) = sum_{dx} V(u+1+dx) - sum_{dx} V(u-1+dx) (terms outside the image dropped, on the
+// few edge lanes only; consecutive columns share their three-column sums) into one of two LDS
+// rows, and every candidate adds M_1 at its track column of row v+1.  The q, V and M_1 rows are
+// double-buffered by row parity, so one barrier per row orders every write before its reads.
+// Rows are padded to the NC * 256 columns the threads own (the columns past W hold zeros), so
+// the column loops carry no bounds test.  The row loop is unrolled nine times so that the ring
+// rotates by renaming registers instead of moving them.
 // mode 0 / 1: G_x w_g with the exponent as printed / squared; mode 2: the prior work's vote
 // |grad| cos(theta_e - theta_Vp) = t . (p - V_p) / |p - V_p| = -dot / |r|, in FP64 (no gate)
 __device__ __forceinline__ float edge_q(const ld_edge& ed, int r, double vx, double vy, float inv_sg2, int sq) {
@@ -1368,6 +1369,10 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         return;
     }
     constexpr int WP = NC * kBlock;  // columns owned by the threads (>= W)
+    // a thread owns NC consecutive columns when NC is odd (a stride coprime with the LDS banks),
+    // else columns t, t + 256, ...
+    constexpr bool kConsec = NC % 2 == 1;
+    auto col = [&](int k) { return kConsec ? t * NC + k : t + k * kBlock; };
     // by row parity: dense q rows; V rows, column u at u + 2 (two zero columns each side); M_1
     // rows (entries >= W stay 0)
     auto qb = [&](int par) -> float* { return fsm + par * WP; };
@@ -1449,7 +1454,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         constexpr int S = decltype(Sc)::value;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const int u = t * NC + k;
+            const int u = col(k);
             ring[k][S] = q[u];
             q[u] = 0.0f;
         }
@@ -1502,7 +1507,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         auto vcol = [&](auto both) {
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                const int u = t * NC + k;
+                const int u = col(k);
                 float r[9];
 #pragma unroll
                 for (int j = 0; j < 9; ++j) r[j] = ring[k][(S + j) % 9];
@@ -1527,21 +1532,31 @@ __global__ __launch_bounds__(kBlock) void k_energy(Dev d, const uint8_t* cand_ma
         __syncthreads();
         float* mrow = mb(par);
         const float* vr = Vp(par);
-        // a thread's NC consecutive columns share their three-column sums: the sum over columns
-        // u-2 .. u (M_0 at u-1) is the one over u .. u+2 (M_0 at u+1) of the column two to the left
-        float vv[NC + 4], T3[NC + 2];
+        // the three-column sums (the one over columns u-2 .. u, M_0 at u-1, is the one over
+        // u .. u+2, M_0 at u+1, of the column two to the left: shared by consecutive columns)
+        float g1[NC], g2[NC];
+        if constexpr (kConsec) {
+            float vv[NC + 4], T3[NC + 2];
 #pragma unroll
-        for (int j = 0; j < NC + 4; ++j) vv[j] = vr[t * NC + j];
+            for (int j = 0; j < NC + 4; ++j) vv[j] = vr[t * NC + j];
 #pragma unroll
-        for (int j = 0; j < NC + 2; ++j) T3[j] = (vv[j] + vv[j + 1]) + vv[j + 2];
+            for (int j = 0; j < NC + 2; ++j) T3[j] = (vv[j] + vv[j + 1]) + vv[j + 2];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) { g1[k] = T3[k + 2]; g2[k] = T3[k]; }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const int u = col(k);
+                g1[k] = (vr[u + 2] + vr[u + 3]) + vr[u + 4];
+                g2[k] = (vr[u] + vr[u + 1]) + vr[u + 2];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            const int u = t * NC + k;
-            const float g1 = T3[k + 2];   // columns u .. u+2 (M_0 at u+1)
-            const float g2 = T3[k];       // columns u-2 .. u (M_0 at u-1)
-            float m1 = g1 - g2;
+            const int u = col(k);
+            float m1 = g1[k] - g2[k];
             // the columns at the image edges and past it (a few lanes of a few waves)
-            if (u < 1 || u >= W - 1) m1 = u < W ? (u + 1 <= W - 1 ? g1 : 0.0f) - (u >= 1 ? g2 : 0.0f) : 0.0f;
+            if (u < 1 || u >= W - 1) m1 = u < W ? (u + 1 <= W - 1 ? g1[k] : 0.0f) - (u >= 1 ? g2[k] : 0.0f) : 0.0f;
             mrow[u] = m1;
         }
         if (v < v_max) candidates(mb(par ^ 1));   // row v + 1
