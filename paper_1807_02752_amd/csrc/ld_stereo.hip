@@ -16,16 +16,17 @@
 // Layout: one workgroup per (frame, map) sweeps the rows from the bottom; the 2 rho + 1 image
 // rows of both images sit in an LDS ring (one new row per step into the slot of the row that
 // leaves, fetched from HBM while the row before it is matched), stored word-interleaved (word g
-// of all slots together) so that a block's words are constant offsets from one address; the sum
-// of products takes the rows in slot order for both blocks, which leaves it unchanged.  The column sums over the ring follow each new row incrementally, the
-// block sums of a row come from the column sums four columns a thread, and the square roots of
-// the block variances are kept per column (FP64), so a candidate costs its 2 rho + 1 rows of
-// byte dot products, a subtraction, a multiplication and a division.  A pixel with a matched
-// neighbour below searches its few propagated candidates in its own lane; a pixel without one
-// (every pixel of the first row) searches all of 1..d_max, which would hold up the 63 other
-// lanes of its wave, so such pixels go to a queue that whole waves take one pixel at a time,
-// a candidate per lane.  The propagation makes the rows of a frame sequential; frames and the
-// two maps are independent workgroups.
+// of all slots together) so that a block's words are constant offsets from one address; the
+// sum of products takes the rows in slot order for both blocks, which leaves it unchanged.  The
+// column sums over the ring follow each new row incrementally, the block sums of a row come
+// from the column sums four columns a thread, and the square roots of the block variances are
+// kept per column (FP64), so a candidate costs its 2 rho + 1 rows of byte dot products, a
+// subtraction, a multiplication and a division.  A pixel with a matched neighbour below scores
+// its few propagated candidates (up to three runs) in one loop of its own lane; a pixel without
+// one (every pixel of the first row) searches all of 1..d_max, which would hold up the 63 other
+// lanes of its wave, so such pixels are queued: many (the first row) are taken one a lane, few
+// one a wave with a candidate per lane and a reduction over the wave.  The propagation makes
+// the rows of a frame sequential; frames and the two maps are independent workgroups.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
