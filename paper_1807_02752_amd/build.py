@@ -26,7 +26,8 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp,
            os.path.join(CSRC, "ld.hip"), os.path.join(CSRC, "ld_server.hip"),
            os.path.join(CSRC, "ld_cnn.hip"), os.path.join(CSRC, "ld_filter.hip"),
-           os.path.join(CSRC, "ld_track.hip"), os.path.join(CSRC, "ld_stereo.hip")]
+           os.path.join(CSRC, "ld_track.hip"), os.path.join(CSRC, "ld_stereo.hip"),
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -2704,6 +2704,7 @@ ld_status ld_frame_set_active(ld_frame f, int32_t n) {
 
 ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint64_t* stream_ids,
                    const int64_t* frame_idx, int32_t* vdisp_out, double* beta_out, void* hip_stream) {
+    LdRange rr_("ld_vdisp");
     if (!f) return LD_E_INVAL;
     if (check_images(f, nullptr, 0, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
     if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
@@ -2719,6 +2720,7 @@ ld_status ld_vdisp(ld_frame f, const void* disp, int64_t disp_pitch, const uint6
 ld_status ld_vp_ransac(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
                        const uint64_t* stream_ids, const int64_t* frame_idx, const double* seed_gamma,
                        double* vp_out, void* hip_stream) {
+    LdRange rr_("ld_vp_ransac");
     if (!f) return LD_E_INVAL;
     if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
     if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
@@ -2732,6 +2734,7 @@ ld_status ld_vp_ransac(ld_frame f, const uint8_t* grey, int64_t grey_pitch, cons
 }
 
 ld_status ld_lane_energy(ld_frame f, const uint8_t* cand_mask, float* energy_out, void* hip_stream) {
+    LdRange rr_("ld_lane_energy");
     if (!f) return LD_E_INVAL;
     if (energy_out && !aligned(energy_out, 4)) return LD_E_INVAL;
     if (f->stage < 2) return LD_E_STATE;
@@ -2743,6 +2746,7 @@ ld_status ld_lane_energy(ld_frame f, const uint8_t* cand_mask, float* energy_out
 }
 
 ld_status ld_peaks(ld_frame f, ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    LdRange rr_("ld_peaks");
     if (!f || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
     if (curves_out && !aligned(curves_out, 4)) return LD_E_INVAL;
     if (f->stage < 3) return LD_E_STATE;
@@ -2755,6 +2759,7 @@ ld_status ld_peaks(ld_frame f, ld_lanes* lanes_out, float* curves_out, void* hip
 ld_status ld_detect(ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp, int64_t disp_pitch,
                     const uint64_t* stream_ids, const int64_t* frame_idx, ld_lanes* lanes_out, float* curves_out,
                     void* hip_stream) {
+    LdRange rr_("ld_detect");
     if (!f || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
     if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;
     if ((stream_ids && !aligned(stream_ids, 8)) || (frame_idx && !aligned(frame_idx, 8))) return LD_E_INVAL;
@@ -2767,6 +2772,7 @@ ld_status ld_detect_noalloc(int32_t width, int32_t height, int32_t batch, int32_
                             const ld_params* p, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                             int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
                             ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    LdRange rr_("ld_detect_noalloc");
     ld_frame_s fr;                      // host state on the stack; prof stays off (no event pool)
     if (init_dev(fr.d, width, height, batch, fmt, d_max, p) != LD_OK) return LD_E_INVAL;
     if (!lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
@@ -2791,6 +2797,7 @@ ld_status ld_detect_noalloc(int32_t width, int32_t height, int32_t batch, int32_
 ld_status ld_detect_pruned(ld_frame f, ld_cnn n, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                            int64_t disp_pitch, const uint64_t* stream_ids, const int64_t* frame_idx,
                            const double* seed_gamma, ld_lanes* lanes_out, float* curves_out, void* hip_stream) {
+    LdRange rr_("ld_detect_pruned");
     if (!f || !n || !lanes_out || !aligned(lanes_out, 4)) return LD_E_INVAL;
     if (seed_gamma && !aligned(seed_gamma, 8)) return LD_E_INVAL;
     if (!grey || check_images(f, grey, grey_pitch, disp, disp_pitch) != LD_OK) return LD_E_INVAL;

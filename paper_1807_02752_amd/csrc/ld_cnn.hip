@@ -1076,12 +1076,14 @@ ld_status ld_cnn_load(const char* path, const ld_cnn_config* cfg, ld_cnn* out) {
 
 ld_status ld_cnn_forward(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                          int64_t disp_pitch, float* prob_out, void* hip_stream) {
+    LdRange rr_("ld_cnn_forward");
     if (prob_out && ((uintptr_t)prob_out % 4) != 0) return LD_E_INVAL;
     return ldi_cnn_bits(n, f, grey, grey_pitch, disp, disp_pitch, prob_out, 0, static_cast<hipStream_t>(hip_stream));
 }
 
 ld_status ld_cnn_labels(ld_cnn n, ld_frame f, const ld_lanes* lanes, const float* curves, float radius,
                         float radius_per_disp, uint8_t* labels_out, void* hip_stream) {
+    LdRange rr_("ld_cnn_labels");
     if (!n || !f || !lanes || !curves || !labels_out || !(radius >= 0.0f) || !(radius_per_disp >= 0.0f))
         return LD_E_INVAL;
     ldi_frame_view V;
@@ -1097,6 +1099,7 @@ ld_status ld_cnn_labels(ld_cnn n, ld_frame f, const ld_lanes* lanes, const float
 ld_status ld_cnn_train_step(ld_cnn n, ld_frame f, const uint8_t* grey, int64_t grey_pitch, const void* disp,
                             int64_t disp_pitch, const uint8_t* labels, float pos_weight, float inv_norm, float lr,
                             float* loss_out, float* grad_out, void* hip_stream) {
+    LdRange rr_("ld_cnn_train_step");
     ldi_frame_view V;
     ld_status s = check_frame(n, f, V, grey, grey_pitch, disp, disp_pitch);
     if (s != LD_OK) return s;

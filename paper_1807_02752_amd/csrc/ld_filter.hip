@@ -129,6 +129,7 @@ void launch(const ldi_frame_view& V, const uint8_t* grey, int64_t gp, uint8_t* o
 extern "C" ld_status ld_bilateral(ld_frame f, const uint8_t* grey, int64_t grey_pitch, uint8_t* out,
                                   int64_t out_pitch, int32_t rho, float sigma_s, float sigma_r, int32_t road_rows,
                                   void* hip_stream) {
+    LdRange rr_("ld_bilateral");
     ldi_frame_view V;
     if (!f || !grey || !out || ldi_frame_get_view(f, &V) != LD_OK) return LD_E_INVAL;
     if (rho < 1 || rho > kMaxRho || !(sigma_s > 0.0f) || !(sigma_r > 0.0f) || !std::isfinite(sigma_s) ||

@@ -3,10 +3,21 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stddef.h>
 #include <stdint.h>
 
 #include "ld.h"
+
+// A roctx range named after an ABI call around its host part (argument checks and the
+// enqueueing of its kernels; the kernels themselves run later on the caller's stream), so a
+// marker trace (rocprofv3 --marker-trace) shows each call beside the kernels it launched.
+struct LdRange {
+    explicit LdRange(const char* name) noexcept { roctxRangePush(name); }
+    ~LdRange() { roctxRangePop(); }
+    LdRange(const LdRange&) = delete;
+    LdRange& operator=(const LdRange&) = delete;
+};
 
 // Kernels of later launches on f skip the frames b >= *d_count (d_count: device int32,
 // nullable to process every launched frame).  Lets one captured graph of a full batch serve

@@ -342,6 +342,7 @@ ld_status ld_server_destroy(ld_server s) {
 
 ld_status ld_server_submit(ld_server s, int32_t stream_id, int32_t cls, const uint8_t* grey, int64_t grey_pitch,
                            const void* disp, int64_t disp_pitch, int64_t* req_out) {
+    LdRange rr_("ld_server_submit");
     if (!s || !grey || !disp || cls < 0 || cls >= s->cfg.n_classes || stream_id < 0 || stream_id >= s->cfg.n_streams)
         return LD_E_INVAL;
     const int W = s->cfg.width[cls], es = elem_size(s->cfg.fmt[cls]);
@@ -366,6 +367,7 @@ ld_status ld_server_submit(ld_server s, int32_t stream_id, int32_t cls, const ui
 }
 
 ld_status ld_server_poll(ld_server s, ld_server_result* results, int32_t max_results, int32_t* n_out) {
+    LdRange rr_("ld_server_poll");
     if (!s || (max_results > 0 && !results) || !n_out) return LD_E_INVAL;
     ld_status status = LD_OK;
     // 1. retire finished batches

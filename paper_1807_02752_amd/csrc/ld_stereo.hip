@@ -412,6 +412,7 @@ void launch(const uint8_t* left, int64_t lp, const uint8_t* right, int64_t rp, c
 extern "C" ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pitch, const uint8_t* right,
                                int64_t right_pitch, int32_t rho, int32_t tau, int32_t tr_lrc, uint8_t* disp_out,
                                int64_t disp_pitch, uint8_t* disp_lf, uint8_t* disp_rt, void* hip_stream) {
+    LdRange rr_("ld_stereo");
     ldi_frame_view V;
     if (!f || !left || !right || !disp_out || !disp_lf || !disp_rt || ldi_frame_get_view(f, &V) != LD_OK)
         return LD_E_INVAL;

@@ -105,6 +105,7 @@ extern "C" void ld_track_params_default(ld_track_params* tp) {
 
 extern "C" ld_status ld_track(ld_frame f, const ld_lanes* lanes, ld_track_state* states, const int32_t* state_index,
                               const ld_track_params* tp, void* hip_stream) {
+    LdRange rr_("ld_track");
     ldi_frame_view V;
     if (!f || !lanes || !states || ldi_frame_get_view(f, &V) != LD_OK) return LD_E_INVAL;
     ld_track_params P;
