@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldref.cpp")
-_SO = os.path.join(_HERE, "libldref.so")
+_SO = os.environ.get("LDREF_SO") or os.path.join(_HERE, "libldref.so")   # LDREF_SO: a sanitizer build
 
 
 def build(force: bool = True) -> str:
