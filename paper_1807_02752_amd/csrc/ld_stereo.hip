@@ -13,9 +13,12 @@
 // The right map is the same search with the roles of the images swapped (the other block at
 // x + d); the check keeps l(u) when |l(u) - l_right(u - l(u))| <= tr.
 //
-// Layout: one workgroup per (frame, map) sweeps the rows from the bottom; the 2 rho + 1 image
-// rows of both images sit in an LDS ring (one new row per step into the slot of the row that
-// leaves, fetched from HBM while the row before it is matched), stored word-interleaved (word g
+// Layout: one workgroup per frame sweeps the rows from the bottom, its two halves the left and
+// the right map in step; each half keeps the statistics of its own image, which the other half
+// reads as its partner's, so an image's ring, column sums, block sums and variances are formed
+// once for both maps.  The 2 rho + 1 image rows of both images sit in LDS rings (one new row
+// per step into the slot of the row that leaves, fetched from HBM while the row before it is
+// matched), stored word-interleaved (word g
 // of all slots together) so that a block's words are constant offsets from one address; the
 // sum of products takes the rows in slot order for both blocks, which leaves it unchanged.  The
 // column sums over the ring follow each new row incrementally, the block sums of a row come
@@ -26,7 +29,7 @@
 // one (every pixel of the first row) searches all of 1..d_max, which would hold up the 63 other
 // lanes of its wave, so such pixels are queued: many (the first row) are taken one a lane, few
 // one a wave with a candidate per lane and a reduction over the wave.  The propagation makes
-// the rows of a frame sequential; frames and the two maps are independent workgroups.
+// the rows of a frame sequential; frames are independent workgroups.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,7 +40,7 @@
 
 namespace {
 
-constexpr int kT = 512;        // sweep threads: 8 waves, two sweeps per CU (LDS) keep 4 waves per SIMD
+constexpr int kT = 512;        // sweep threads per map: a workgroup holds both maps of a frame, 16 waves
 constexpr int kWaves = kT / 64;
 constexpr int kRowWords = 2;   // words of a new row per thread and image: widths up to 4 kT kRowWords
 constexpr int kPad = 8;        // zero columns on both sides of the column sums (block sums four at a time)
@@ -55,12 +58,12 @@ size_t stereo_lds(int W, int rho) {
            + 4 * sizeof(int32_t) * (Wp + 2 * kPad)     // column sums S, Q of both images
            + 2 * sizeof(int32_t) * Wp                  // block sums S of both images
            + 2 * sizeof(double) * Wp                   // sqrt of the block variances of both images
-           + 2 * Wp                                    // disparities of the previous and the current row
-           + sizeof(uint16_t) * Wp + 16;               // queue of full-range pixels, its length
+           + 4 * Wp                                    // disparities of the previous and the current row, both maps
+           + 2 * sizeof(uint16_t) * Wp + 16;           // queues of full-range pixels and their lengths, both maps
 }
 
 template <int RHO>
-__global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, const uint8_t* right, int64_t rp,
+__global__ __launch_bounds__(2 * kT) void k_stereo(const uint8_t* left, int64_t lp, const uint8_t* right, int64_t rp,
                                                int W, int H, const int32_t* nact, int nframes, int d_max, int tau,
                                                uint8_t* lf, uint8_t* rt) {
     constexpr int K = 2 * RHO + 1, N = K * K;
@@ -83,62 +86,70 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
     const int b = blockIdx.x, t = threadIdx.x;
     const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
     if (b >= nf) return;
-    const bool is_left = blockIdx.y == 0;
-    // the map's own image is a (blocks at u), the other b (blocks at u - d or u + d)
-    const uint8_t* ga = (is_left ? left + (int64_t)b * H * lp : right + (int64_t)b * H * rp);
-    const uint8_t* gb = (is_left ? right + (int64_t)b * H * rp : left + (int64_t)b * H * lp);
-    const int64_t pa = is_left ? lp : rp, pb = is_left ? rp : lp;
-    uint8_t* out = (is_left ? lf : rt) + (int64_t)b * H * W;
-    const int sgn = is_left ? -1 : 1;
+    // the workgroup's first half sweeps the left map (own image left, blocks of the right image
+    // at u - d), the second the right map (own image right, blocks of the left image at u + d);
+    // each half keeps the ring, column sums, block sums and variances of its own image, which
+    // the other half reads as the partner's
+    const int m = t / kT, tm = t % kT;
+    const uint8_t* ga = (m == 0 ? left + (int64_t)b * H * lp : right + (int64_t)b * H * rp);
+    const int64_t pa = m == 0 ? lp : rp;
+    uint8_t* out = (m == 0 ? lf : rt) + (int64_t)b * H * W;
+    const int sgn = m == 0 ? -1 : 1;
     const int Wp = (W + 3) / 4 * 4, Wq = Wp / 4;
-    uint32_t* ringA = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* ringB = ringA + K * Wq;
-    uint8_t* ringA8 = smem;
-    uint8_t* ringB8 = reinterpret_cast<uint8_t*>(ringB);
-    int32_t* colS_a = reinterpret_cast<int32_t*>(smem + round16(2 * (size_t)K * Wp)) + kPad;
-    int32_t* colQ_a = colS_a + Wp + 2 * kPad;
-    int32_t* colS_b = colQ_a + Wp + 2 * kPad;
-    int32_t* colQ_b = colS_b + Wp + 2 * kPad;
-    int32_t* S_a = colQ_b + Wp + kPad;
-    int32_t* S_b = S_a + Wp;
-    double* sq_a = reinterpret_cast<double*>(S_b + Wp);
-    double* sq_b = sq_a + Wp;
-    uint8_t* prev = reinterpret_cast<uint8_t*>(sq_b + Wp);
-    uint8_t* cur = prev + Wp;
-    uint16_t* queue = reinterpret_cast<uint16_t*>(cur + Wp);
-    int* qn = reinterpret_cast<int*>(queue + Wp);
+    uint32_t* ring0 = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* ring1 = ring0 + K * Wq;
+    int32_t* colS0 = reinterpret_cast<int32_t*>(smem + round16(2 * (size_t)K * Wp)) + kPad;
+    int32_t* colQ0 = colS0 + Wp + 2 * kPad;
+    int32_t* colS1 = colQ0 + Wp + 2 * kPad;
+    int32_t* colQ1 = colS1 + Wp + 2 * kPad;
+    int32_t* S0 = colQ1 + Wp + kPad;
+    int32_t* S1 = S0 + Wp;
+    double* sq0 = reinterpret_cast<double*>(S1 + Wp);
+    double* sq1 = sq0 + Wp;
+    uint8_t* pc = reinterpret_cast<uint8_t*>(sq1 + Wp);
+    uint16_t* queues = reinterpret_cast<uint16_t*>(pc + 4 * Wp);
+    int* qns = reinterpret_cast<int*>(queues + 2 * Wp);
+    uint32_t* ringA = m == 0 ? ring0 : ring1;
+    uint32_t* ringB = m == 0 ? ring1 : ring0;
+    uint8_t* ringA8 = reinterpret_cast<uint8_t*>(ringA);
+    int32_t* colS_a = m == 0 ? colS0 : colS1;
+    int32_t* colQ_a = m == 0 ? colQ0 : colQ1;
+    int32_t* S_a = m == 0 ? S0 : S1;
+    const int32_t* S_b = m == 0 ? S1 : S0;
+    double* sq_a = m == 0 ? sq0 : sq1;
+    const double* sq_b = m == 0 ? sq1 : sq0;
+    uint8_t* prev = pc + (2 * m) * Wp;
+    uint8_t* cur = pc + (2 * m + 1) * Wp;
+    uint16_t* queue = queues + m * Wp;
+    int* qn = qns + m;
     // rows outside the matched band are 0 (every row when no block fits)
     const bool none = W < K || H < K;
     for (int v = 0; v < H; ++v) {
         if (!none && v >= RHO && v <= H - 1 - RHO) continue;
-        for (int u = t; u < W; u += kT) out[(int64_t)v * W + u] = 0;
+        for (int u = tm; u < W; u += kT) out[(int64_t)v * W + u] = 0;
     }
     if (none) return;
-    // the first 2 rho + 1 rows (slot v mod K), bytes past the width cleared; the column sums
+    // the first 2 rho + 1 rows of the own image (slot v mod K), bytes past the width cleared;
+    // its column sums
     const int vb = H - 1 - RHO;
     for (int v = vb - RHO; v <= vb + RHO; ++v) {
         const int slot = v % K;
-        for (int u = t; u < Wp; u += kT) {
-            const int at = ((u >> 2) * K + slot) * 4 + (u & 3);
-            ringA8[at] = u < W ? ga[(int64_t)v * pa + u] : 0;
-            ringB8[at] = u < W ? gb[(int64_t)v * pb + u] : 0;
-        }
+        for (int u = tm; u < Wp; u += kT) ringA8[((u >> 2) * K + slot) * 4 + (u & 3)] = u < W ? ga[(int64_t)v * pa + u] : 0;
     }
-    for (int i = t; i < kPad; i += kT) {
-        colS_a[-1 - i] = colQ_a[-1 - i] = colS_b[-1 - i] = colQ_b[-1 - i] = 0;
-        colS_a[Wp + i] = colQ_a[Wp + i] = colS_b[Wp + i] = colQ_b[Wp + i] = 0;
+    for (int i = tm; i < kPad; i += kT) {
+        colS_a[-1 - i] = colQ_a[-1 - i] = 0;
+        colS_a[Wp + i] = colQ_a[Wp + i] = 0;
     }
-    if (t == 0) *qn = 0;
+    if (tm == 0) *qn = 0;
     __syncthreads();
-    for (int u = t; u < Wp; u += kT) {
-        int sa = 0, qa = 0, sb = 0, qb = 0;
+    for (int u = tm; u < Wp; u += kT) {
+        int sa = 0, qa = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const int at = ((u >> 2) * K + j) * 4 + (u & 3);
-            const int x = ringA8[at], y = ringB8[at];
-            sa += x; qa += x * x; sb += y; qb += y * y;
+            const int x = ringA8[((u >> 2) * K + j) * 4 + (u & 3)];
+            sa += x; qa += x * x;
         }
-        colS_a[u] = sa; colQ_a[u] = qa; colS_b[u] = sb; colQ_b[u] = qb;
+        colS_a[u] = sa; colQ_a[u] = qa;
     }
     // the candidate of disparity d for the pixel at u: its cost against the best so far (bc
     // starts at -inf), the first strictly larger one kept (with d increasing that leaves ties to
@@ -175,12 +186,13 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         const bool more = v > RHO;             // a row v - rho - 1 follows
         const int vlo = v - RHO;
         __syncthreads();
-        // block sums and sqrt(n Q - S^2), four columns a thread (0 where no block fits)
-        for (int g = t; g < Wq; g += kT) {
-            int cs[4][4 * (2 * kC + 1)];
-            const int32_t* arr[4] = {colS_a, colQ_a, colS_b, colQ_b};
+        // block sums and sqrt(n Q - S^2) of the own image, four columns a thread (0 where no
+        // block fits)
+        for (int g = tm; g < Wq; g += kT) {
+            int cs[2][4 * (2 * kC + 1)];
+            const int32_t* arr[2] = {colS_a, colQ_a};
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < 2; ++a) {
 #pragma unroll
                 for (int c = -kC; c <= kC; ++c) {
                     const int4 q = *reinterpret_cast<const int4*>(arr[a] + 4 * (g + c));
@@ -188,60 +200,50 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
                     cs[a][4 * (c + kC) + 2] = q.z; cs[a][4 * (c + kC) + 3] = q.w;
                 }
             }
-            int bs[4][4];
+            int bs[2][4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                int s = 0;
+            for (int a = 0; a < 2; ++a) {
+                int s_ = 0;
 #pragma unroll
-                for (int m = -RHO; m <= RHO; ++m) s += cs[a][4 * kC + m];
-                bs[a][0] = s;
+                for (int mm = -RHO; mm <= RHO; ++mm) s_ += cs[a][4 * kC + mm];
+                bs[a][0] = s_;
 #pragma unroll
                 for (int i = 1; i < 4; ++i) {
-                    s += cs[a][4 * kC + i + RHO] - cs[a][4 * kC + i - 1 - RHO];
-                    bs[a][i] = s;
+                    s_ += cs[a][4 * kC + i + RHO] - cs[a][4 * kC + i - 1 - RHO];
+                    bs[a][i] = s_;
                 }
             }
-            int4 oa, ob;
-            double qa4[4], qb4[4];
+            int4 oa;
+            double qa4[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 4 * g + i;
                 const bool fits = u >= RHO && u <= W - 1 - RHO;
-                const int sa = fits ? bs[0][i] : 0, sb = fits ? bs[2][i] : 0;
-                const int va = N * bs[1][i] - bs[0][i] * bs[0][i], vbv = N * bs[3][i] - bs[2][i] * bs[2][i];
+                const int va = N * bs[1][i] - bs[0][i] * bs[0][i];
                 qa4[i] = fits && va > 0 ? sqrt((double)va) : 0.0;
-                qb4[i] = fits && vbv > 0 ? sqrt((double)vbv) : 0.0;
-                (&oa.x)[i] = sa; (&ob.x)[i] = sb;
+                (&oa.x)[i] = fits ? bs[0][i] : 0;
             }
             *reinterpret_cast<int4*>(S_a + 4 * g) = oa;
-            *reinterpret_cast<int4*>(S_b + 4 * g) = ob;
 #pragma unroll
-            for (int i = 0; i < 4; i += 2) {
+            for (int i = 0; i < 4; i += 2)
                 *reinterpret_cast<double2*>(sq_a + 4 * g + i) = make_double2(qa4[i], qa4[i + 1]);
-                *reinterpret_cast<double2*>(sq_b + 4 * g + i) = make_double2(qb4[i], qb4[i + 1]);
-            }
         }
         __syncthreads();
-        // the next row from HBM while this one is matched: four bytes a word for words t and
-        // t + kT, byte loads at clamped positions (their values are masked when the words are
-        // put together), so that nothing waits for them before the row is done
-        uint32_t ra[kRowWords][4], rb[kRowWords][4];
+        // the own image's next row from HBM while this one is matched: four bytes a word for
+        // words tm and tm + kT, byte loads at clamped positions (their values are masked when
+        // the words are put together), so that nothing waits for them before the row is done
+        uint32_t ra[kRowWords][4];
         {
             const uint8_t* pa0 = ga + (int64_t)(more ? vlo - 1 : vlo) * pa;
-            const uint8_t* pb0 = gb + (int64_t)(more ? vlo - 1 : vlo) * pb;
 #pragma unroll
             for (int k = 0; k < kRowWords; ++k)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int u = min(4 * (t + k * kT) + i, W - 1);
-                    ra[k][i] = pa0[u];
-                    rb[k][i] = pb0[u];
-                }
+                for (int i = 0; i < 4; ++i) ra[k][i] = pa0[min(4 * (tm + k * kT) + i, W - 1)];
         }
         // pixels with a matched neighbour below: the union of [l - tau, l + tau] over those
         // neighbours, in increasing d, in the pixel's own lane; the others are queued
         const bool first = v == vb;
-        for (int u = t; u < W; u += kT) {
+        for (int u = tm; u < W; u += kT) {
             int best = 0;
             if (u >= RHO && u <= W - 1 - RHO && sq_a[u] > 0.0) {
                 int l0 = 0, l1 = 0, l2 = 0;
@@ -297,74 +299,67 @@ __global__ __launch_bounds__(kT) void k_stereo(const uint8_t* left, int64_t lp, 
         __syncthreads();
         // queued pixels: many (the first row) one a lane over all of 1..d_max; few one a wave,
         // candidates 1 + lane, 65 + lane, ..., then the best (largest cost, then smallest d)
-        // over the wave
+        // over the wave.  Both halves take the barrier when either map queued any.
         const int nq = *qn;
-        if (nq >= kT / 2) {
-            for (int q = t; q < nq; q += kT) {
-                const int u = queue[q];
-                uint32_t A[K][NW];
-                own_block(u, A);
-                const int Sa = S_a[u];
-                const double da = sq_a[u];
-                int best = 0;
-                double bc = -__builtin_inf();
-                for (int d = 1; d <= d_max; ++d) score(A, u, Sa, da, d, best, bc);
-                cur[u] = (uint8_t)best;
-            }
-            __syncthreads();
-        } else if (nq > 0) {
-            const int wv = t >> 6, lane = t & 63;
-            for (int q = wv; q < nq; q += kWaves) {
-                const int u = queue[q];
-                uint32_t A[K][NW];
-                own_block(u, A);
-                const int Sa = S_a[u];
-                const double da = sq_a[u];
-                int best = 0;
-                double bc = -__builtin_inf();
-                for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, best, bc);
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double oc = __shfl_xor(bc, off);
-                    const int od = __shfl_xor(best, off);
-                    if (od != 0 && (best == 0 || oc > bc || (oc == bc && od < best))) { best = od; bc = oc; }
+        if (qns[0] > 0 || qns[1] > 0) {
+            if (nq >= kT / 2) {
+                for (int q = tm; q < nq; q += kT) {
+                    const int u = queue[q];
+                    uint32_t A[K][NW];
+                    own_block(u, A);
+                    const int Sa = S_a[u];
+                    const double da = sq_a[u];
+                    int best = 0;
+                    double bc = -__builtin_inf();
+                    for (int d = 1; d <= d_max; ++d) score(A, u, Sa, da, d, best, bc);
+                    cur[u] = (uint8_t)best;
                 }
-                if (lane == 0) cur[u] = (uint8_t)best;
+            } else if (nq > 0) {
+                const int wv = tm >> 6, lane = tm & 63;
+                for (int q = wv; q < nq; q += kWaves) {
+                    const int u = queue[q];
+                    uint32_t A[K][NW];
+                    own_block(u, A);
+                    const int Sa = S_a[u];
+                    const double da = sq_a[u];
+                    int best = 0;
+                    double bc = -__builtin_inf();
+                    for (int d = 1 + lane; d <= d_max; d += 64) score(A, u, Sa, da, d, best, bc);
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const double oc = __shfl_xor(bc, off);
+                        const int od = __shfl_xor(best, off);
+                        if (od != 0 && (best == 0 || oc > bc || (oc == bc && od < best))) { best = od; bc = oc; }
+                    }
+                    if (lane == 0) cur[u] = (uint8_t)best;
+                }
             }
             __syncthreads();
         }
-        // the next row replaces row v + rho in the ring and in the column sums; the row out
+        // the own image's next row replaces row v + rho in its ring and column sums; the row out
         if (more) {
             const int slot = (v + RHO) % K;
 #pragma unroll
             for (int k = 0; k < kRowWords; ++k) {
-                const int g = t + k * kT;
+                const int g = tm + k * kT;
                 if (g >= Wq) continue;
-                uint32_t na = 0, nb = 0;
+                uint32_t na = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (4 * g + i < W) {
-                        na |= ra[k][i] << (8 * i);
-                        nb |= rb[k][i] << (8 * i);
-                    }
-                }
-                const uint32_t oa = ringA[g * K + slot], ob = ringB[g * K + slot];
-                ringA[g * K + slot] = na; ringB[g * K + slot] = nb;
+                for (int i = 0; i < 4; ++i)
+                    if (4 * g + i < W) na |= ra[k][i] << (8 * i);
+                const uint32_t oa = ringA[g * K + slot];
+                ringA[g * K + slot] = na;
                 int4 s1 = *reinterpret_cast<int4*>(colS_a + 4 * g), q1 = *reinterpret_cast<int4*>(colQ_a + 4 * g);
-                int4 s2 = *reinterpret_cast<int4*>(colS_b + 4 * g), q2 = *reinterpret_cast<int4*>(colQ_b + 4 * g);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int xn = (na >> (8 * i)) & 0xFF, xo = (oa >> (8 * i)) & 0xFF;
-                    const int yn = (nb >> (8 * i)) & 0xFF, yo = (ob >> (8 * i)) & 0xFF;
                     (&s1.x)[i] += xn - xo; (&q1.x)[i] += xn * xn - xo * xo;
-                    (&s2.x)[i] += yn - yo; (&q2.x)[i] += yn * yn - yo * yo;
                 }
                 *reinterpret_cast<int4*>(colS_a + 4 * g) = s1; *reinterpret_cast<int4*>(colQ_a + 4 * g) = q1;
-                *reinterpret_cast<int4*>(colS_b + 4 * g) = s2; *reinterpret_cast<int4*>(colQ_b + 4 * g) = q2;
             }
         }
-        for (int u = t; u < W; u += kT) out[(int64_t)v * W + u] = cur[u];
-        if (t == 0) *qn = 0;
+        for (int u = tm; u < W; u += kT) out[(int64_t)v * W + u] = cur[u];
+        if (tm == 0) *qn = 0;
         uint8_t* tmp = prev; prev = cur; cur = tmp;
     }
 }
@@ -403,7 +398,7 @@ void launch(const uint8_t* left, int64_t lp, const uint8_t* right, int64_t rp, c
     const size_t lds = stereo_lds(V.W, RHO);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_stereo<RHO>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_stereo<RHO>, dim3(V.active, 2), dim3(kT), lds, st, left, lp, right, rp, V.W, V.H, V.nact,
+    hipLaunchKernelGGL(k_stereo<RHO>, dim3(V.active), dim3(2 * kT), lds, st, left, lp, right, rp, V.W, V.H, V.nact,
                        V.active, V.d_max, tau, lf, rt);
 }
 
