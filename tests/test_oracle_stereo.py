@@ -54,12 +54,12 @@ def test_shifted_texture_is_recovered_with_cost_one():
     assert not out[:rho].any() and not out[:, :rho].any()
 
 
-def test_factorised_cost_equals_the_definition():
-    rng = np.random.default_rng(2)
+@pytest.mark.parametrize("rho", [1, 3, 5])
+def test_factorised_cost_equals_the_definition(rho):
+    rng = np.random.default_rng(2 + rho)
     L = _texture(rng, 24, 50)
     R = np.clip(np.roll(L, -5, axis=1).astype(int) + rng.integers(-30, 31, L.shape), 0, 255).astype(np.uint8)
-    out, lf, rt, cost = oracle.stereo(L, R, d_max=12)
-    rho = 3
+    out, lf, rt, cost = oracle.stereo(L, R, d_max=12, rho=rho)
     for v in range(rho, 24 - rho):
         for u in range(rho + 1, 50 - rho):
             d = int(lf[v, u])
