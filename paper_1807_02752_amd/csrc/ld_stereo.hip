@@ -392,6 +392,36 @@ __global__ __launch_bounds__(kTL) void k_lrc(const uint8_t* lf, const uint8_t* r
     }
 }
 
+// The same check over the maps as one flat array when the left map and the output are whole
+// words apart and the output rows are contiguous: a thread loads a word of four disparities,
+// gathers their right-map partners (same row: u - l >= 0) and stores a word.
+__global__ __launch_bounds__(256) void k_lrc_words(const uint8_t* lf, const uint8_t* rt, int W, int64_t HW,
+                                                  const int32_t* nact, int nframes, int tr, uint8_t* out) {
+    const int nf = nact != nullptr ? min(*nact, nframes) : nframes;
+    const int64_t total = (int64_t)nf * HW;
+    const int64_t p0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (p0 >= total) return;
+    const int64_t row = p0 / W;
+    int u = (int)(p0 - row * W);
+    if (p0 + 4 <= total) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(lf + p0);
+        uint32_t o = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int l = (int)((w >> (8 * i)) & 0xFFu);
+            const int ui = u + i < W ? u + i : u + i - W;     // a word spans at most two rows
+            if (l > 0 && ui - l >= 0 && abs(l - (int)rt[p0 + i - l]) <= tr) o |= (uint32_t)l << (8 * i);
+        }
+        *reinterpret_cast<uint32_t*>(out + p0) = o;
+    } else {
+        for (int64_t p = p0; p < total; ++p, ++u) {      // the last few bytes
+            if (u == W) u = 0;
+            const int l = lf[p];
+            out[p] = (l > 0 && u - l >= 0 && abs(l - (int)rt[p - l]) <= tr) ? (uint8_t)l : 0;
+        }
+    }
+}
+
 template <int RHO>
 void launch(const uint8_t* left, int64_t lp, const uint8_t* right, int64_t rp, const ldi_frame_view& V, int tau,
             uint8_t* lf, uint8_t* rt, hipStream_t st) {
@@ -423,9 +453,16 @@ extern "C" ld_status ld_stereo(ld_frame f, const uint8_t* left, int64_t left_pit
             case 4: launch<4>(left, left_pitch, right, right_pitch, V, tau, disp_lf, disp_rt, st); break;
             default: launch<5>(left, left_pitch, right, right_pitch, V, tau, disp_lf, disp_rt, st); break;
         }
-        const unsigned gx = (unsigned)((V.H + kLrcRows - 1) / kLrcRows);
-        hipLaunchKernelGGL(k_lrc<kLrcPx>, dim3(gx, V.active), dim3(kTL), 0, st, disp_lf, disp_rt, V.W, V.H, V.nact,
-                           V.active, tr_lrc, disp_out, disp_pitch);
+        const int64_t HW = (int64_t)V.W * V.H;
+        if (disp_pitch == V.W && ((uintptr_t)disp_lf & 3) == 0 && ((uintptr_t)disp_out & 3) == 0) {
+            const int64_t words = (V.active * HW + 3) / 4;
+            hipLaunchKernelGGL(k_lrc_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, disp_lf, disp_rt,
+                               V.W, HW, V.nact, V.active, tr_lrc, disp_out);
+        } else {
+            const unsigned gx = (unsigned)((V.H + kLrcRows - 1) / kLrcRows);
+            hipLaunchKernelGGL(k_lrc<kLrcPx>, dim3(gx, V.active), dim3(kTL), 0, st, disp_lf, disp_rt, V.W, V.H,
+                               V.nact, V.active, tr_lrc, disp_out, disp_pitch);
+        }
     }
     if (hipGetLastError() != hipSuccess) return LD_E_HIP;
     return ldi_frame_set_last(f, hip_stream);
